@@ -1,0 +1,161 @@
+#!/usr/bin/env python3
+"""Benchmark: geodesic RK4 lane-steps per second on one MI355X (Kerr, FP64).
+
+Workload (one benchmark "step" = one pass of the hot path over the batch):
+Kerr M = 1, a = 0.9, 1,048,576 timelike bound geodesics drawn on the device
+(r0 in [5, 50], theta0 in [pi/4, 3pi/4], E in [0.92, 0.98], L_z in [2.5, 4.5],
+Carter Q in [0, 12], accepted when the radial and polar potentials are >= 0,
+random signs of u^r and u^theta, seed 2), then: reset the state, invariant
+monitor, 20,000 fixed RK4 steps of h = 0.02 M in FP64 with horizon/escape
+termination, invariant monitor.  Inputs are resident in HBM before timing.
+
+value = sum over lanes of the RK4 steps each lane took / wall time of the timed
+steps.  roofline: FP64 vector ALU bound; achieved = algorithmic flops per
+lane-step (static count, FLOPS_PER_STEP_F64) x lane-steps of one integrate
+launch / that launch's average duration (HIP events on its stream).
+cpu_baseline: the oracle (plain C, FP64) on a strided sample of the same
+workload, on the host's cores.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP64_VECTOR_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 128 FP64 flop/clk/CU
+
+
+def parse():
+    p = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=3)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--lanes", type=int, default=1 << 20)
+    p.add_argument("--rk-steps", type=int, default=20000)
+    p.add_argument("--block", type=int, default=0)
+    p.add_argument("--cpu-lanes", type=int, default=1024,
+                   help="oracle sample: this many strided lanes x the full step count")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    return p.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on exactly one GPU (--gpus 1); multi-GPU runs are "
+              "not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1803_08320_amd import LIB_PATH
+    if not os.path.exists(LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    import paper_1803_08320_amd as m
+
+    torch.cuda.set_device(0)
+    st = [(1.0, 0.9)]
+    n, n_rk, h = args.lanes, args.rk_steps, 0.02
+    spec = m.ICSpec(mode=m.IC_CONSTANTS, seed=2)
+    s0, consts, attempts = m.init_particles(spec, st, n)
+    state = torch.empty_like(s0)
+    status, steps = m.new_lane_arrays(n)
+    inv0 = torch.empty((4, n), dtype=torch.float64, device="cuda")
+    inv1 = torch.empty_like(inv0)
+    torch.cuda.synchronize()
+
+    def one_step(ev=None):
+        state.copy_(s0)
+        status.zero_()
+        steps.zero_()
+        m.invariants(state, st, out=inv0)
+        if ev:
+            ev[0].record()
+        m.integrate(state, status, steps, st, h=h, n_steps=n_rk, block=args.block)
+        if ev:
+            ev[1].record()
+        m.invariants(state, st, out=inv1)
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    lane_steps = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        one_step(evs[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    per_step_lane_steps = int(steps.sum().item())
+    lane_steps = per_step_lane_steps * args.steps
+    wall = t1 - t0
+    kern_ms = [a.elapsed_time(b) for a, b in evs]
+    avg_kern_s = sum(kern_ms) / len(kern_ms) / 1e3
+    achieved = m.FLOPS_PER_STEP_F64 * per_step_lane_steps / avg_kern_s / 1e12
+
+    # physics of the last step: conserved-quantity drift on lanes still active
+    i0, i1 = inv0.cpu().numpy(), inv1.cpu().numpy()
+    act = status.cpu().numpy() == 0
+    dE = np.abs(i1[0] / i0[0] - 1)[act]
+    Qok = act & (i0[2] >= 0.1)
+    dQ = np.abs(i1[2] / i0[2] - 1)[Qok]
+
+    result = {
+        "metric": "geodesic RK4 steps/sec on 1 GPU (Kerr), FP64 vs FP32-comp at stated dQ/Q",
+        "value": lane_steps / wall,
+        "unit": "lane-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "kerr_a0.9_bound_timelike_1M_lanes_20000_steps_h0.02_fp64",
+                   "lanes": n, "rk4_steps": n_rk, "h": h, "spin": 0.9, "seed": 2,
+                   "block": args.block or 256},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR_TFLOPS,
+                     "traffic": None, "kernel": "rk4_f64_kernel",
+                     "flops_per_lane_step": m.FLOPS_PER_STEP_F64,
+                     "kernel_ms_avg": 1e3 * avg_kern_s},
+        "physics": {"active_frac": float(act.mean()),
+                    "dE_over_E_p99": float(np.quantile(dE, 0.99)) if dE.size else None,
+                    "dQ_over_Q_p99": float(np.quantile(dQ, 0.99)) if dQ.size else None,
+                    "dQ_over_Q_max": float(dQ.max()) if dQ.size else None},
+        "context": {"paper_gpu_lane_steps_per_s": 3.69e6,
+                    "paper_hardware": "GTX 960M, Kerr a=0.5, h=0.1, FP64, no I/O"},
+    }
+
+    if not args.no_cpu_baseline:
+        import oracle
+        k = max(1, n // args.cpu_lanes)
+        idx = list(range(0, n, k))[: args.cpu_lanes]
+        ranges = (spec.r_range, spec.th_range, spec.E_range, spec.Lz_range, spec.Q_range)
+        cols = [oracle.ic_constants(2, st, 1, ranges, lane0=i)[1] for i in idx]
+        sc = np.concatenate(cols, axis=1)
+        nthreads = oracle.max_threads()
+        t = time.perf_counter()
+        _, _, ref_steps = oracle.integrate(st, sc, h, n_rk, nthreads=nthreads)
+        dt = time.perf_counter() - t
+        result["cpu_baseline"] = {"value": float(ref_steps.sum()) / dt, "unit": "lane-steps/s",
+                                  "cores": nthreads, "kind": "oracle",
+                                  "sample": "%d strided lanes of the workload x %d RK4 steps "
+                                            "(%.1f s wall)" % (len(idx), n_rk, dt)}
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,215 @@
+/*
+ * malbec.h - C ABI of the MI355X (gfx950) batched geodesic RK4 integrator.
+ *
+ * The method is that of G. D. Quiroga, "MALBEC: a new CUDA-C ray-tracer in
+ * General Relativity" (arXiv:1803.08320): timelike and null geodesics of the
+ * Kerr metric in Boyer-Lindquist coordinates (Section 2, eq. kerr; a = 0 is
+ * Schwarzschild, Section 4), one independent particle or photon per lane,
+ * advanced with the classic fourth-order Runge-Kutta method (Section 5), and
+ * stopped per lane at the event horizon (Section 5: r <= 1 + sqrt(1 - a^2) for
+ * M = 1).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Units G = c = 1.  Coordinates x = (t, r, theta, phi), affine parameter tau
+ *    (proper time for timelike geodesics).
+ *  - State layout: double state[8 * n], component-major ("SoA"):
+ *      state[k * n + i], k = 0..7 = (t, r, theta, phi, u^t, u^r, u^theta, u^phi),
+ *    u^mu = dx^mu / dtau.  The geodesic ODE is dx/dtau = u,
+ *    du^mu/dtau = -Gamma^mu_{ab} u^a u^b.
+ *  - Pointers: "device" pointers are HIP device memory of the current device
+ *    (for example torch tensors' data_ptr()); "host" pointers are CPU memory.
+ *    Every buffer is owned by the caller.  The library allocates no device
+ *    memory: scratch space, where needed, is the caller's workspace `ws`.
+ *  - Streams: `stream` is a hipStream_t passed as void* (NULL = null stream).
+ *    Device work is enqueued asynchronously on it; a return of MALBEC_OK means
+ *    the arguments were valid and the launches were enqueued, not that they
+ *    finished.  Per-lane physics outcomes are lane status codes, never call
+ *    errors.
+ *  - Errors: every call returns one of the MALBEC_E* codes below; the text of
+ *    the last error on the calling host thread is malbec_last_error().  On an
+ *    argument error nothing is enqueued and no buffer is touched.
+ *  - Calls on different streams are independent; calls that write the same
+ *    buffers must be ordered by the caller.
+ */
+#ifndef MALBEC_H
+#define MALBEC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define MALBEC_API __attribute__((visibility("default")))
+#else
+#define MALBEC_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ---------------------------------------------------------------- */
+#define MALBEC_OK 0
+#define MALBEC_EINVAL (-1)  /* bad argument: null pointer, n < 0, M <= 0, a < 0 or a > M,
+                               h <= 0, n_steps < 0, unknown enum, table too large */
+#define MALBEC_ENOMEM (-2)  /* caller workspace smaller than malbec_workspace_bytes() */
+#define MALBEC_EDEVICE (-3) /* a HIP runtime error (text in malbec_last_error()) */
+#define MALBEC_ENOTSUP (-4) /* valid but unsupported combination */
+
+/* ---- lane status (int32 per lane) ------------------------------------------------ */
+#define MALBEC_ACTIVE 0    /* still integrating */
+#define MALBEC_HORIZON 1   /* reached r <= horizon_factor * r_+ (Section 5 stop rule) */
+#define MALBEC_ESCAPE 2    /* reached r >= r_escape */
+#define MALBEC_DISK 3      /* crossed the thin equatorial disk (camera) */
+#define MALBEC_NONFINITE 4 /* step result non-finite or theta left (0, pi) */
+#define MALBEC_BUDGET 5    /* camera ray still active after max_steps */
+
+/* ---- enums ----------------------------------------------------------------------- */
+#define MALBEC_F64 0       /* FP64 throughout */
+#define MALBEC_F32_KAHAN 1 /* FP32 state with compensated update, FP64 near the horizon */
+
+#define MALBEC_IC_CANONICAL 0 /* the paper's initial-condition rows (Section 5 table) */
+#define MALBEC_IC_CIRCULAR 1  /* equatorial near-circular orbits (Sections 3-4) */
+#define MALBEC_IC_CONSTANTS 2 /* random (E, L_z, Carter Q) with potential rejection */
+
+#define MALBEC_MAX_SPACETIMES 64
+
+#define MALBEC_OP_INTEGRATE 1
+#define MALBEC_OP_CAMERA 2
+
+/* One Kerr spacetime: mass M > 0 and spin a in [0, M] (Section 2; a > M is a naked
+ * singularity and is rejected). */
+typedef struct {
+    double M;
+    double a;
+} malbec_spacetime;
+
+/* A batch may mix spacetimes: lane i uses st[st_of_lane[i]]. */
+typedef struct {
+    const malbec_spacetime *st; /* host, n_st entries (copied during the call) */
+    int32_t n_st;               /* 1 .. MALBEC_MAX_SPACETIMES */
+    int32_t pad_;
+    const int32_t *st_of_lane;  /* device, n entries in [0, n_st), or NULL: all lanes use st[0] */
+} malbec_batch;
+
+/* Initial-condition recipe (malbec_init_particles). */
+typedef struct {
+    int32_t mode;   /* MALBEC_IC_* */
+    int32_t pad0_;
+    uint64_t seed;  /* SplitMix64 seed: draw k of attempt j of lane i is output
+                       (i*2^24 + j*2^4 + k + 1) of the SplitMix64 sequence from `seed` */
+    int64_t lane0;  /* global index of lane 0 of this call (sub-batches draw the same numbers) */
+    double mu2;     /* 1 timelike, 0 null (CONSTANTS mode) */
+    /* CIRCULAR: r0 = U[r_lo, r_hi), L = L_circ(r0) (1 + dL (2U - 1)), theta = pi/2,
+       u^r = u^theta = 0; E from g(u,u) = -1 if e_from_norm else E_circ(r0). */
+    double r_lo, r_hi, dL;
+    int32_t prograde, e_from_norm;
+    /* CONSTANTS: per attempt draw r0, theta0, E, L_z, Q uniformly in the ranges and the
+       signs of u^r, u^theta; accept iff R(r0) >= 0 and Theta(theta0) >= 0. */
+    double r_range[2], th_range[2], E_range[2], Lz_range[2], Q_range[2];
+    int64_t max_attempts; /* lanes that exhaust it get NaN state and attempts = max_attempts */
+    /* CANONICAL: device, n rows of 8 doubles (t, r, theta, phi, p_t, p_r, p_theta, p_phi),
+       row-major as in the paper's IC table, with the paper's sign p_t = +E. */
+    const double *rows;
+} malbec_ic_spec;
+
+/* Integration controls (malbec_integrate). */
+typedef struct {
+    double h;                /* affine step, > 0 */
+    int64_t n_steps;         /* RK4 steps per ACTIVE lane in this call, >= 0 */
+    int32_t precision;       /* MALBEC_F64 or MALBEC_F32_KAHAN */
+    int32_t block;           /* threads per block (multiple of 64, <= 1024), 0 = default */
+    double horizon_factor;   /* stop at r <= horizon_factor * r_+ ; >= 1 (1.01 typical) */
+    double r_escape;         /* stop at r >= r_escape */
+    double fp64_zone_factor; /* F32_KAHAN: steps starting at r < factor * r_+ run in FP64 */
+    int32_t steps_per_chunk; /* steps per kernel launch, 0 = all n_steps in one launch */
+    int32_t checkpoint_every;/* K > 0: write the state every K steps (see malbec_integrate) */
+} malbec_run;
+
+/* Camera (malbec_trace_camera): Bardeen image plane of a static observer at
+ * (r_obs, theta = incl, phi = 0); pixel p = j * nx + i, alpha = -w + (i + 1/2) 2w / nx,
+ * beta = -w + (j + 1/2) 2w / ny.  Photon: E = 1, L_z = -alpha sin(incl),
+ * Q = beta^2 + cos^2(incl) (alpha^2 - a^2), arriving with u^r > 0 and
+ * sign(u^theta) = sign(beta); traced backward by negating u.  Step
+ * h = h0 * max(1, r_n / h_r0).  Disk: thin, equatorial, disk_r_in <= r <= disk_r_out
+ * (disk_r_in <= 0 selects the prograde ISCO). */
+typedef struct {
+    double M, a;
+    double r_obs, incl, half_width;
+    int32_t nx, ny;
+    double h0, h_r0;
+    double r_escape, horizon_factor;
+    double disk_r_in, disk_r_out;
+    int64_t max_steps;
+    int32_t block;           /* threads per block, 0 = default */
+    int32_t steps_per_chunk; /* steps between retire/refill checks, 0 = default */
+    int32_t persistent;      /* 1: persistent work-queue kernel (default), 0: one lane per pixel */
+    int32_t pad_;
+} malbec_camera;
+
+/* Text of the last error on this host thread ("" if none).  Valid until the next
+ * call on the same thread. */
+MALBEC_API const char *malbec_last_error(void);
+
+/* Library version as 10000 * major + 100 * minor + patch. */
+MALBEC_API int malbec_version(void);
+
+/* Bytes of caller workspace an operation needs: op = MALBEC_OP_INTEGRATE (n lanes) or
+ * MALBEC_OP_CAMERA (n = nx * ny pixels).  Returns 0 for operations that need none. */
+MALBEC_API size_t malbec_workspace_bytes(int32_t op, int64_t n);
+
+/* Build the initial state of n lanes on the device (one GPU thread per lane).
+ * spec: host.  b: host (st_of_lane device or NULL).  state: device, 8n doubles (out).
+ * consts: device, 4n doubles (out, nullable): (E, L_z, Q, mu2) component-major;
+ * attempts: device, n int64 (out, nullable): draws used by the CONSTANTS sampler.
+ * Passages: Section 5 IC table (CANONICAL; u^mu = g^{mu nu} p_nu with p_t = -E),
+ * Sections 3-4 circular orbits (CIRCULAR), Carter's separated equations (CONSTANTS).
+ * Errors: MALBEC_EINVAL on bad arguments; lanes whose sampler is exhausted are
+ * reported through attempts == max_attempts and a NaN state, not as an error. */
+MALBEC_API int malbec_init_particles(const malbec_ic_spec *spec, const malbec_batch *b, int64_t n,
+                          double *state, double *consts, int64_t *attempts, void *stream);
+
+/* Advance every ACTIVE lane by up to run->n_steps classic RK4 steps of size run->h
+ * (Section 5).  state: device 8n (in/out); status, steps: device n int32 (in/out;
+ * steps accumulates the steps each lane evaluated).  After each step the lane stops,
+ * in this order, when: an RK4 stage point lies at r <= horizon_factor r_+ (HORIZON,
+ * the step's start state kept); the result is non-finite or has theta outside (0, pi)
+ * (NONFINITE, start state kept); r <= horizon_factor r_+ (HORIZON); r >= r_escape
+ * (ESCAPE).  Lanes not ACTIVE on entry are not touched.  Calling twice with n_steps/2
+ * gives bitwise the same result as one call with n_steps.
+ * checkpoints: device (nullable, F64 only): if run->checkpoint_every = K > 0, slot
+ * s = 0 .. n_steps/K receives the state after s*K steps of this call, at
+ * checkpoints[s * 8n + k * n + i]; a lane stopped earlier repeats its final state.
+ * ws / ws_bytes: caller workspace (malbec_workspace_bytes(MALBEC_OP_INTEGRATE, n)).
+ * Errors: MALBEC_EINVAL, MALBEC_ENOMEM, MALBEC_EDEVICE. */
+MALBEC_API int malbec_integrate(const malbec_run *run, const malbec_batch *b, int64_t n, double *state,
+                     int32_t *status, int32_t *steps, double *checkpoints, void *ws,
+                     size_t ws_bytes, void *stream);
+
+/* Trace the nx * ny pixels of a camera backward until each photon stops (status
+ * HORIZON, ESCAPE, DISK, NONFINITE or BUDGET), with the rules of malbec_integrate
+ * plus: DISK when the equatorial plane is crossed between y_n and y_{n+1}
+ * (signbit of cos theta differs) at r_c = r_n + (r_{n+1} - r_n) c_n / (c_n - c_{n+1})
+ * inside [disk_r_in, disk_r_out] (checked after NONFINITE, before HORIZON).
+ * status, steps: device nx*ny int32 (out).  hit: device 2*nx*ny doubles (out),
+ * component-major (r_c, phi_c), NaN unless DISK.  final_state: device 8*nx*ny
+ * (out, nullable).  ws: caller workspace of malbec_workspace_bytes(MALBEC_OP_CAMERA,
+ * nx*ny) bytes (the persistent kernel's work counter).
+ * Errors: MALBEC_EINVAL, MALBEC_ENOMEM, MALBEC_EDEVICE. */
+MALBEC_API int malbec_trace_camera(const malbec_camera *cam, int32_t *status, int32_t *steps, double *hit,
+                        double *final_state, void *ws, size_t ws_bytes, void *stream);
+
+/* Invariants of n states: out (device, 4n doubles, component-major) =
+ * (E, L_z, Q, g(u,u)) with E = -(g_tt u^t + g_tphi u^phi) and L_z = g_tphi u^t +
+ * g_phiphi u^phi (the conserved momenta, dp_t/dtau = dp_phi/dtau = 0 in Sections 3-4),
+ * Carter's Q = (rho^2 u^theta)^2 + cos^2 theta [a^2 (mu^2 - E^2) + L_z^2 / sin^2 theta]
+ * with mu^2 = -g(u,u), and the norm g(u,u) (= -1 timelike, eq. geo; 0 null).
+ * Errors: MALBEC_EINVAL, MALBEC_EDEVICE. */
+MALBEC_API int malbec_invariants(const malbec_batch *b, int64_t n, const double *state, double *out,
+                      void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MALBEC_H */

@@ -1,0 +1,310 @@
+"""MI355X-native batched RK4 integrator of Kerr geodesics (Python binding).
+
+Thin ctypes binding over ``libmalbec.so`` (the C ABI in ``include/malbec.h``).
+Each function marshals torch tensors (device memory, current HIP stream) into
+the C call of the same name; every step of the computation runs in the HIP
+kernels of the library.  There is no CPU fallback: importing this module on a
+machine without the built library raises, and calling it without a GPU fails
+in the HIP runtime.
+
+Method: G. D. Quiroga, "MALBEC: a new CUDA-C ray-tracer in General
+Relativity" (arXiv:1803.08320): Kerr metric in Boyer-Lindquist coordinates
+(Section 2), classic RK4 (Section 5), per-lane horizon stop (Section 5).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+from typing import Optional, Sequence, Tuple
+
+import torch  # noqa: F401  (loads the HIP runtime before libmalbec)
+
+__all__ = [
+    "ICSpec", "Camera", "init_particles", "integrate", "invariants", "trace_camera",
+    "workspace_bytes", "last_error", "version", "lib", "MalbecError", "STATUS",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmalbec.so")
+
+STATUS = {"ACTIVE": 0, "HORIZON": 1, "ESCAPE": 2, "DISK": 3, "NONFINITE": 4, "BUDGET": 5}
+F64, F32_KAHAN = 0, 1
+IC_CANONICAL, IC_CIRCULAR, IC_CONSTANTS = 0, 1, 2
+OP_INTEGRATE, OP_CAMERA = 1, 2
+MAX_SPACETIMES = 64
+
+# Algorithmic FP64 flops of one RK4 step of one lane as implemented (static count of
+# csrc/kerr_accel.hpp by csrc/flopcount.cpp: add/sub/mul/div 1, fma 2, sincos 2).
+FLOPS_PER_STEP_F64 = 582
+
+
+class MalbecError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("malbec error %d: %s" % (code, msg))
+        self.code = code
+
+
+# ---- C structures (layout of include/malbec.h) ---------------------------------------
+class c_spacetime(C.Structure):
+    _fields_ = [("M", C.c_double), ("a", C.c_double)]
+
+
+class c_batch(C.Structure):
+    _fields_ = [("st", C.POINTER(c_spacetime)), ("n_st", C.c_int32), ("pad_", C.c_int32),
+                ("st_of_lane", C.c_void_p)]
+
+
+class c_ic_spec(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("pad0_", C.c_int32), ("seed", C.c_uint64),
+                ("lane0", C.c_int64), ("mu2", C.c_double), ("r_lo", C.c_double),
+                ("r_hi", C.c_double), ("dL", C.c_double), ("prograde", C.c_int32),
+                ("e_from_norm", C.c_int32), ("r_range", C.c_double * 2),
+                ("th_range", C.c_double * 2), ("E_range", C.c_double * 2),
+                ("Lz_range", C.c_double * 2), ("Q_range", C.c_double * 2),
+                ("max_attempts", C.c_int64), ("rows", C.c_void_p)]
+
+
+class c_run(C.Structure):
+    _fields_ = [("h", C.c_double), ("n_steps", C.c_int64), ("precision", C.c_int32),
+                ("block", C.c_int32), ("horizon_factor", C.c_double), ("r_escape", C.c_double),
+                ("fp64_zone_factor", C.c_double), ("steps_per_chunk", C.c_int32),
+                ("checkpoint_every", C.c_int32)]
+
+
+class c_camera(C.Structure):
+    _fields_ = [("M", C.c_double), ("a", C.c_double), ("r_obs", C.c_double),
+                ("incl", C.c_double), ("half_width", C.c_double), ("nx", C.c_int32),
+                ("ny", C.c_int32), ("h0", C.c_double), ("h_r0", C.c_double),
+                ("r_escape", C.c_double), ("horizon_factor", C.c_double),
+                ("disk_r_in", C.c_double), ("disk_r_out", C.c_double), ("max_steps", C.c_int64),
+                ("block", C.c_int32), ("steps_per_chunk", C.c_int32), ("persistent", C.c_int32),
+                ("pad_", C.c_int32)]
+
+
+EXPORTS = {
+    "malbec_last_error": (C.c_char_p, []),
+    "malbec_version": (C.c_int, []),
+    "malbec_workspace_bytes": (C.c_size_t, [C.c_int32, C.c_int64]),
+    "malbec_init_particles": (C.c_int, [C.POINTER(c_ic_spec), C.POINTER(c_batch), C.c_int64,
+                                        C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "malbec_integrate": (C.c_int, [C.POINTER(c_run), C.POINTER(c_batch), C.c_int64, C.c_void_p,
+                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
+                                   C.c_void_p]),
+    "malbec_trace_camera": (C.c_int, [C.POINTER(c_camera), C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "malbec_invariants": (C.c_int, [C.POINTER(c_batch), C.c_int64, C.c_void_p, C.c_void_p,
+                                    C.c_void_p]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libmalbec.so (built in-tree by ``__graft_entry__.build()``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libmalbec.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().malbec_last_error().decode()
+
+
+def version() -> int:
+    return lib().malbec_version()
+
+
+def workspace_bytes(op: int, n: int) -> int:
+    return lib().malbec_workspace_bytes(op, n)
+
+
+def _check(rc):
+    if rc != 0:
+        raise MalbecError(rc, last_error())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor], dtype=None, numel=None, name="tensor"):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError("%s must have dtype %s, got %s" % (name, dtype, t.dtype))
+    if numel is not None and t.numel() != numel:
+        raise ValueError("%s must have %d elements, got %d" % (name, numel, t.numel()))
+    return C.c_void_p(t.data_ptr())
+
+
+class _Batch:
+    """Holds the ctypes batch descriptor and keeps its arrays alive."""
+
+    def __init__(self, spacetimes, st_of_lane: Optional[torch.Tensor], n: int):
+        sts = [tuple(map(float, s)) for s in spacetimes]
+        if not 1 <= len(sts) <= MAX_SPACETIMES:
+            raise ValueError("need 1..%d spacetimes" % MAX_SPACETIMES)
+        self.arr = (c_spacetime * len(sts))(*[c_spacetime(M, a) for M, a in sts])
+        self.c = c_batch(C.cast(self.arr, C.POINTER(c_spacetime)), len(sts), 0,
+                         _ptr(st_of_lane, torch.int32, n, "st_of_lane"))
+
+
+def _spacetimes(spacetimes):
+    if isinstance(spacetimes, tuple) and len(spacetimes) == 2 and not hasattr(spacetimes[0], "__len__"):
+        return [spacetimes]
+    return list(spacetimes)
+
+
+@dataclass
+class ICSpec:
+    """Initial-condition recipe, see malbec_ic_spec in include/malbec.h."""
+    mode: int = IC_CONSTANTS
+    seed: int = 0
+    lane0: int = 0
+    mu2: float = 1.0
+    r_lo: float = 6.5
+    r_hi: float = 20.0
+    dL: float = 0.0
+    prograde: bool = True
+    e_from_norm: bool = True
+    r_range: Tuple[float, float] = (5.0, 50.0)
+    th_range: Tuple[float, float] = (0.7853981633974483, 2.356194490192345)
+    E_range: Tuple[float, float] = (0.92, 0.98)
+    Lz_range: Tuple[float, float] = (2.5, 4.5)
+    Q_range: Tuple[float, float] = (0.0, 12.0)
+    max_attempts: int = 100000
+    rows: Optional[torch.Tensor] = field(default=None, repr=False)
+
+    def to_c(self, n):
+        return c_ic_spec(self.mode, 0, self.seed & 0xFFFFFFFFFFFFFFFF, self.lane0, self.mu2,
+                         self.r_lo, self.r_hi, self.dL, int(self.prograde), int(self.e_from_norm),
+                         (C.c_double * 2)(*self.r_range), (C.c_double * 2)(*self.th_range),
+                         (C.c_double * 2)(*self.E_range), (C.c_double * 2)(*self.Lz_range),
+                         (C.c_double * 2)(*self.Q_range), self.max_attempts,
+                         _ptr(self.rows, torch.float64, 8 * n if self.rows is not None else None,
+                              "rows"))
+
+
+def init_particles(spec: ICSpec, spacetimes, n: int, st_of_lane: Optional[torch.Tensor] = None,
+                   device="cuda", want_consts=True, want_attempts=True):
+    """Build n initial states on the device.  Returns (state[8, n], consts[4, n] or None,
+    attempts[n] or None)."""
+    dev = torch.device(device)
+    state = torch.empty((8, n), dtype=torch.float64, device=dev)
+    consts = torch.empty((4, n), dtype=torch.float64, device=dev) if want_consts else None
+    attempts = torch.empty(n, dtype=torch.int64, device=dev) if want_attempts else None
+    b = _Batch(_spacetimes(spacetimes), st_of_lane, n)
+    cs = spec.to_c(n)
+    _check(lib().malbec_init_particles(C.byref(cs), C.byref(b.c), n, _ptr(state),
+                                       _ptr(consts), _ptr(attempts), _stream()))
+    return state, consts, attempts
+
+
+def integrate(state: torch.Tensor, status: torch.Tensor, steps: torch.Tensor, spacetimes,
+              h: float, n_steps: int, horizon_factor: float = 1.01, r_escape: float = 1500.0,
+              precision: str = "f64", fp64_zone_factor: float = 1.2, block: int = 0,
+              steps_per_chunk: int = 0, st_of_lane: Optional[torch.Tensor] = None,
+              checkpoints: Optional[torch.Tensor] = None, checkpoint_every: int = 0,
+              ws: Optional[torch.Tensor] = None):
+    """Advance state[8, n] in place (status, steps int32[n] in/out)."""
+    n = state.shape[-1]
+    prec = {"f64": F64, "f32k": F32_KAHAN}[precision]
+    run = c_run(h, n_steps, prec, block, horizon_factor, r_escape, fp64_zone_factor,
+                steps_per_chunk, checkpoint_every)
+    b = _Batch(_spacetimes(spacetimes), st_of_lane, n)
+    if checkpoint_every > 0:
+        if checkpoints is None:
+            raise ValueError("checkpoint_every > 0 needs a checkpoints tensor")
+        slots = n_steps // checkpoint_every + 1
+        if checkpoints.numel() < slots * 8 * n:
+            raise ValueError("checkpoints must hold %d slots of 8 x %d doubles" % (slots, n))
+    need = workspace_bytes(OP_INTEGRATE, n)
+    if need and ws is None:
+        ws = torch.empty(need, dtype=torch.uint8, device=state.device)
+    _check(lib().malbec_integrate(C.byref(run), C.byref(b.c), n,
+                                  _ptr(state, torch.float64, 8 * n, "state"),
+                                  _ptr(status, torch.int32, n, "status"),
+                                  _ptr(steps, torch.int32, n, "steps"),
+                                  _ptr(checkpoints, torch.float64, None, "checkpoints"),
+                                  _ptr(ws), ws.numel() if ws is not None else 0, _stream()))
+
+
+def invariants(state: torch.Tensor, spacetimes, st_of_lane: Optional[torch.Tensor] = None,
+               out: Optional[torch.Tensor] = None):
+    """(E, L_z, Q, g(u,u)) of each lane as a [4, n] device tensor."""
+    n = state.shape[-1]
+    if out is None:
+        out = torch.empty((4, n), dtype=torch.float64, device=state.device)
+    b = _Batch(_spacetimes(spacetimes), st_of_lane, n)
+    _check(lib().malbec_invariants(C.byref(b.c), n, _ptr(state, torch.float64, 8 * n, "state"),
+                                   _ptr(out, torch.float64, 4 * n, "out"), _stream()))
+    return out
+
+
+@dataclass
+class Camera:
+    """Camera of malbec_trace_camera (include/malbec.h)."""
+    M: float = 1.0
+    a: float = 0.998
+    r_obs: float = 1000.0
+    incl: float = 1.0471975511965976
+    half_width: float = 25.0
+    nx: int = 2048
+    ny: int = 2048
+    h0: float = 0.1
+    h_r0: float = 10.0
+    r_escape: float = 1500.0
+    horizon_factor: float = 1.01
+    disk_r_in: float = -1.0
+    disk_r_out: float = 30.0
+    max_steps: int = 100000
+    block: int = 0
+    steps_per_chunk: int = 0
+    persistent: int = 1
+
+    def to_c(self):
+        return c_camera(self.M, self.a, self.r_obs, self.incl, self.half_width, self.nx, self.ny,
+                        self.h0, self.h_r0, self.r_escape, self.horizon_factor, self.disk_r_in,
+                        self.disk_r_out, self.max_steps, self.block, self.steps_per_chunk,
+                        self.persistent, 0)
+
+
+def trace_camera(cam: Camera, final_state: bool = False, device="cuda", out=None, ws=None):
+    """Trace every pixel; returns dict(status[n], steps[n], hit[2, n], final_state[8, n]?)."""
+    npix = cam.nx * cam.ny
+    dev = torch.device(device)
+    if out is None:
+        out = {"status": torch.empty(npix, dtype=torch.int32, device=dev),
+               "steps": torch.empty(npix, dtype=torch.int32, device=dev),
+               "hit": torch.empty((2, npix), dtype=torch.float64, device=dev)}
+        if final_state:
+            out["final_state"] = torch.empty((8, npix), dtype=torch.float64, device=dev)
+    need = workspace_bytes(OP_CAMERA, npix)
+    if ws is None:
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    cc = cam.to_c()
+    _check(lib().malbec_trace_camera(C.byref(cc), _ptr(out["status"], torch.int32, npix),
+                                     _ptr(out["steps"], torch.int32, npix),
+                                     _ptr(out["hit"], torch.float64, 2 * npix),
+                                     _ptr(out.get("final_state"), torch.float64, None),
+                                     _ptr(ws), ws.numel(), _stream()))
+    return out
+
+
+def new_lane_arrays(n: int, device="cuda"):
+    """Zeroed (status, steps) int32 arrays for n ACTIVE lanes."""
+    return (torch.zeros(n, dtype=torch.int32, device=device),
+            torch.zeros(n, dtype=torch.int32, device=device))

@@ -1,0 +1,206 @@
+// C ABI entry points of libmalbec: argument validation, error text, dispatch to
+// the kernel launchers of the other translation units.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "internal.hpp"
+
+namespace malbec {
+
+static thread_local char g_err[512];
+
+int fail(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+void clear_error() { g_err[0] = '\0'; }
+
+int make_table(const malbec_batch *b, double horizon_factor, double zone_factor, StTable &T)
+{
+    if (!b || !b->st) return fail(MALBEC_EINVAL, "batch or batch->st is NULL");
+    if (b->n_st < 1 || b->n_st > kMaxSt)
+        return fail(MALBEC_EINVAL, "n_st = %d outside [1, %d]", b->n_st, kMaxSt);
+    if (!(horizon_factor >= 1.0) || !isfinite(horizon_factor))
+        return fail(MALBEC_EINVAL, "horizon_factor = %g must be >= 1", horizon_factor);
+    T.n_st = b->n_st;
+    for (int k = 0; k < b->n_st; ++k) {
+        double M = b->st[k].M, a = b->st[k].a;
+        if (!(M > 0.0) || !isfinite(M)) return fail(MALBEC_EINVAL, "spacetime %d: M = %g must be > 0", k, M);
+        if (!(a >= 0.0) || !(a <= M))
+            return fail(MALBEC_EINVAL, "spacetime %d: a = %g outside [0, M = %g]", k, a, M);
+        double rp = M + sqrt(M * M - a * a);
+        T.st[k].M = M;
+        T.st[k].a = a;
+        T.st[k].r_stop = horizon_factor * rp;
+        T.st[k].r_zone = zone_factor * rp;
+    }
+    for (int k = b->n_st; k < kMaxSt; ++k) T.st[k] = T.st[0];
+    return MALBEC_OK;
+}
+
+}  // namespace malbec
+
+using namespace malbec;
+
+extern "C" {
+
+const char *malbec_last_error(void) { return g_err; }
+
+int malbec_version(void) { return 10000 * 0 + 100 * 3 + 0; }
+
+size_t malbec_workspace_bytes(int32_t op, int64_t n)
+{
+    (void)n;
+    if (op == MALBEC_OP_CAMERA) return 256;  // work counter (own cache line)
+    return 0;
+}
+
+int malbec_init_particles(const malbec_ic_spec *spec, const malbec_batch *b, int64_t n,
+                          double *state, double *consts, int64_t *attempts, void *stream)
+{
+    clear_error();
+    if (!spec) return fail(MALBEC_EINVAL, "spec is NULL");
+    if (n < 0) return fail(MALBEC_EINVAL, "n = %lld < 0", (long long)n);
+    if (n > 0 && !state) return fail(MALBEC_EINVAL, "state is NULL");
+    StTable T;
+    int rc = make_table(b, 1.0, 1.0, T);
+    if (rc) return rc;
+    switch (spec->mode) {
+    case MALBEC_IC_CANONICAL:
+        if (n > 0 && !spec->rows) return fail(MALBEC_EINVAL, "CANONICAL mode needs spec->rows");
+        break;
+    case MALBEC_IC_CIRCULAR:
+        if (!(spec->r_lo > 0) || !(spec->r_hi >= spec->r_lo))
+            return fail(MALBEC_EINVAL, "CIRCULAR: need 0 < r_lo <= r_hi");
+        break;
+    case MALBEC_IC_CONSTANTS:
+        if (spec->max_attempts < 1 || spec->max_attempts >= (1 << 20))
+            return fail(MALBEC_EINVAL, "max_attempts = %lld outside [1, 2^20)",
+                        (long long)spec->max_attempts);
+        if (!(spec->mu2 == 0.0 || spec->mu2 == 1.0))
+            return fail(MALBEC_EINVAL, "mu2 = %g must be 0 (null) or 1 (timelike)", spec->mu2);
+        {
+            const double *rg[5] = {spec->r_range, spec->th_range, spec->E_range, spec->Lz_range,
+                                   spec->Q_range};
+            for (int k = 0; k < 5; ++k)
+                if (!(rg[k][1] >= rg[k][0]) || !isfinite(rg[k][0]) || !isfinite(rg[k][1]))
+                    return fail(MALBEC_EINVAL, "range %d is empty or not finite", k);
+        }
+        break;
+    default:
+        return fail(MALBEC_EINVAL, "unknown IC mode %d", spec->mode);
+    }
+    if (spec->lane0 < 0 || spec->lane0 + n > ((int64_t)1 << 39))
+        return fail(MALBEC_EINVAL, "lane range exceeds the 2^39 counter space");
+    if (n == 0) return MALBEC_OK;
+    return launch_init(*spec, T, b->st_of_lane, n, state, consts, attempts, (hipStream_t)stream);
+}
+
+int malbec_integrate(const malbec_run *run, const malbec_batch *b, int64_t n, double *state,
+                     int32_t *status, int32_t *steps, double *checkpoints, void *ws,
+                     size_t ws_bytes, void *stream)
+{
+    clear_error();
+    (void)ws;
+    if (!run) return fail(MALBEC_EINVAL, "run is NULL");
+    if (n < 0) return fail(MALBEC_EINVAL, "n = %lld < 0", (long long)n);
+    if (n > 0 && (!state || !status || !steps))
+        return fail(MALBEC_EINVAL, "state, status and steps must be non-NULL");
+    if (n > ((int64_t)1 << 40)) return fail(MALBEC_EINVAL, "n too large");
+    if (!(run->h > 0.0) || !isfinite(run->h)) return fail(MALBEC_EINVAL, "h = %g must be > 0", run->h);
+    if (run->n_steps < 0 || run->n_steps > INT32_MAX)
+        return fail(MALBEC_EINVAL, "n_steps = %lld outside [0, 2^31)", (long long)run->n_steps);
+    if (!(run->r_escape > 0.0)) return fail(MALBEC_EINVAL, "r_escape must be > 0");
+    if (run->block < 0 || run->block > 1024 || (run->block % 64) != 0)
+        return fail(MALBEC_EINVAL, "block = %d must be a multiple of 64 in [64, 1024] or 0", run->block);
+    if (run->steps_per_chunk < 0) return fail(MALBEC_EINVAL, "steps_per_chunk < 0");
+    if (run->checkpoint_every < 0) return fail(MALBEC_EINVAL, "checkpoint_every < 0");
+    if (run->checkpoint_every > 0 && !checkpoints)
+        return fail(MALBEC_EINVAL, "checkpoint_every > 0 needs a checkpoints buffer");
+    size_t need = malbec_workspace_bytes(MALBEC_OP_INTEGRATE, n);
+    if (ws_bytes < need || (need > 0 && !ws))
+        return fail(MALBEC_ENOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, need);
+    double zone = run->precision == MALBEC_F32_KAHAN ? run->fp64_zone_factor : 1.0;
+    StTable T;
+    int rc = make_table(b, run->horizon_factor, zone, T);
+    if (rc) return rc;
+    if (n == 0 || run->n_steps == 0) {
+        if (run->checkpoint_every > 0 && n > 0)
+            return fail(MALBEC_ENOTSUP, "checkpoints with n_steps = 0");
+        return MALBEC_OK;
+    }
+    if (run->precision == MALBEC_F64)
+        return launch_integrate_f64(*run, T, b->st_of_lane, n, state, status, steps, checkpoints,
+                                    (hipStream_t)stream);
+    if (run->precision == MALBEC_F32_KAHAN) {
+        if (run->checkpoint_every > 0)
+            return fail(MALBEC_ENOTSUP, "checkpoints are FP64 only");
+        if (!(run->fp64_zone_factor >= 1.0))
+            return fail(MALBEC_EINVAL, "fp64_zone_factor = %g must be >= 1", run->fp64_zone_factor);
+        return launch_integrate_f32k(*run, T, b->st_of_lane, n, state, status, steps,
+                                     (hipStream_t)stream);
+    }
+    return fail(MALBEC_EINVAL, "unknown precision %d", run->precision);
+}
+
+int malbec_trace_camera(const malbec_camera *cam, int32_t *status, int32_t *steps, double *hit,
+                        double *final_state, void *ws, size_t ws_bytes, void *stream)
+{
+    clear_error();
+    if (!cam) return fail(MALBEC_EINVAL, "cam is NULL");
+    if (cam->nx < 1 || cam->ny < 1) return fail(MALBEC_EINVAL, "nx, ny must be >= 1");
+    int64_t npix = (int64_t)cam->nx * cam->ny;
+    if (npix > ((int64_t)1 << 31) - 1) return fail(MALBEC_EINVAL, "nx * ny too large");
+    if (!status || !steps || !hit) return fail(MALBEC_EINVAL, "status, steps and hit must be non-NULL");
+    if (!(cam->M > 0.0) || !(cam->a >= 0.0) || !(cam->a <= cam->M))
+        return fail(MALBEC_EINVAL, "need M > 0 and 0 <= a <= M");
+    if (!(cam->r_obs > 0.0) || !(cam->incl > 0.0) || !(cam->incl < M_PI))
+        return fail(MALBEC_EINVAL, "need r_obs > 0 and 0 < incl < pi");
+    if (!(cam->half_width > 0.0)) return fail(MALBEC_EINVAL, "half_width must be > 0");
+    if (!(cam->h0 > 0.0) || !(cam->h_r0 > 0.0)) return fail(MALBEC_EINVAL, "need h0 > 0 and h_r0 > 0");
+    if (!(cam->horizon_factor >= 1.0)) return fail(MALBEC_EINVAL, "horizon_factor must be >= 1");
+    if (!(cam->r_escape > cam->r_obs))
+        return fail(MALBEC_EINVAL, "r_escape must exceed r_obs");
+    if (cam->max_steps < 1 || cam->max_steps > INT32_MAX)
+        return fail(MALBEC_EINVAL, "max_steps outside [1, 2^31)");
+    if (cam->block < 0 || cam->block > 1024 || (cam->block % 64) != 0)
+        return fail(MALBEC_EINVAL, "block must be a multiple of 64 in [64, 1024] or 0");
+    if (cam->steps_per_chunk < 0) return fail(MALBEC_EINVAL, "steps_per_chunk < 0");
+    size_t need = malbec_workspace_bytes(MALBEC_OP_CAMERA, npix);
+    if (ws_bytes < need || !ws)
+        return fail(MALBEC_ENOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, need);
+    double M = cam->M, a = cam->a;
+    double rp = M + sqrt(M * M - a * a);
+    double r_in = cam->disk_r_in;
+    if (r_in <= 0.0) {
+        // prograde ISCO (Bardeen, Press & Teukolsky 1972)
+        double chi = a / M;
+        double Z1 = 1.0 + cbrt(1.0 - chi * chi) * (cbrt(1.0 + chi) + cbrt(1.0 - chi));
+        double Z2 = sqrt(3.0 * chi * chi + Z1 * Z1);
+        r_in = M * (3.0 + Z2 - sqrt((3.0 - Z1) * (3.0 + Z1 + 2.0 * Z2)));
+    }
+    return launch_camera(*cam, cam->horizon_factor * rp, r_in, status, steps, hit, final_state, ws,
+                         (hipStream_t)stream);
+}
+
+int malbec_invariants(const malbec_batch *b, int64_t n, const double *state, double *out,
+                      void *stream)
+{
+    clear_error();
+    if (n < 0) return fail(MALBEC_EINVAL, "n < 0");
+    if (n > 0 && (!state || !out)) return fail(MALBEC_EINVAL, "state and out must be non-NULL");
+    StTable T;
+    int rc = make_table(b, 1.0, 1.0, T);
+    if (rc) return rc;
+    if (n == 0) return MALBEC_OK;
+    return launch_invariants(T, b->st_of_lane, n, state, out, (hipStream_t)stream);
+}
+
+}  // extern "C"

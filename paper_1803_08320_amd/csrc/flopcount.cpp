@@ -1,0 +1,54 @@
+// Static operation count of one FP64 RK4 step as implemented (host tool).
+//
+// Instantiates the same templates the kernels use (kerr_accel.hpp) with a
+// counting scalar type.  Counting rule: add, sub, mul, div = 1 flop each,
+// fma = 2 flops, sincos = 2 (two results), negation = 0.  The count is
+// independent of the data (the code is straight-line), so one evaluation gives
+// the algorithmic flops per lane-step used for the roofline.
+//   g++ -O0 -std=c++17 flopcount.cpp -o flopcount && ./flopcount
+#include <cstdio>
+
+struct Counted;
+static long g_flops = 0, g_div = 0, g_fma = 0, g_addmul = 0;
+
+struct Counted {
+    double v;
+    Counted(double x = 0.0) : v(x) {}
+};
+static Counted op(double v, int flops) { g_flops += flops; if (flops == 1) ++g_addmul; return Counted(v); }
+inline Counted operator+(Counted a, Counted b) { return op(a.v + b.v, 1); }
+inline Counted operator-(Counted a, Counted b) { return op(a.v - b.v, 1); }
+inline Counted operator*(Counted a, Counted b) { return op(a.v * b.v, 1); }
+inline Counted operator/(Counted a, Counted b) { ++g_div; g_flops += 1; return Counted(a.v / b.v); }
+inline Counted operator-(Counted a) { return Counted(-a.v); }
+inline Counted &operator+=(Counted &a, Counted b) { a = a + b; return a; }
+inline Counted fma(Counted a, Counted b, Counted c) { ++g_fma; g_flops += 2; return Counted(a.v * b.v + c.v); }
+
+#include <cmath>
+#include "kerr_accel.hpp"
+
+struct AccelCount {
+    Counted M, a;
+    void operator()(Counted r, Counted th, Counted ut, Counted ur, Counted uth, Counted uph,
+                    Counted &at, Counted &ar, Counted &ath, Counted &aph) const
+    {
+        g_flops += 2;  // sincos
+        Counted s(std::sin(th.v)), c(std::cos(th.v));
+        malbec::kerr_accel<Counted>(M, a, r, s, c, ut, ur, uth, uph, at, ar, ath, aph);
+    }
+};
+
+int main()
+{
+    Counted y[8] = {0.0, 7.0, 1.1, 0.0, 1.2, 0.1, 0.02, 0.05}, y1[8], sr[3];
+    AccelCount f{Counted(1.0), Counted(0.9)};
+    Counted at, ar, ath, aph;
+    g_flops = g_div = g_fma = g_addmul = 0;
+    f(y[1], y[2], y[4], y[5], y[6], y[7], at, ar, ath, aph);
+    long rhs = g_flops, rhs_div = g_div, rhs_fma = g_fma, rhs_am = g_addmul;
+    g_flops = g_div = g_fma = g_addmul = 0;
+    malbec::rk4_step(f, Counted(0.02), y, y1, sr);
+    std::printf("rhs_flops %ld\nrhs_div %ld\nrhs_fma %ld\nrhs_addmul %ld\nstep_flops %ld\nstep_fma %ld\nstep_addmul %ld\nstep_div %ld\n",
+                rhs, rhs_div, rhs_fma, rhs_am, g_flops, g_fma, g_addmul, g_div);
+    return 0;
+}

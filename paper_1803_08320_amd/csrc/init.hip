@@ -1,0 +1,214 @@
+// Initial-condition construction on the device, one thread per lane.
+//
+//  CANONICAL  the paper's IC table rows (t, r, theta, phi, p_t, p_r, p_theta, p_phi)
+//             with p_t = +E (Section 5); u^mu = g^{mu nu} p_nu with p_t -> -E.
+//  CIRCULAR   equatorial circular orbits (Sections 3-4) in the Bardeen-Press-
+//             Teukolsky form, with a seeded relative perturbation of L.
+//  CONSTANTS  seeded (r0, theta0, E, L_z, Q, signs) accepted when Carter's radial
+//             and polar potentials are non-negative; u from the separated equations.
+// Random numbers: SplitMix64 (Steele, Lea & Flood 2014) used as a counter-based
+// generator, draw k of attempt j of lane i = output (i*2^24 + j*2^4 + k + 1) of the
+// sequence started at `seed`.
+#include "internal.hpp"
+
+namespace malbec {
+
+namespace {
+
+__device__ __forceinline__ uint64_t splitmix_out(uint64_t seed, uint64_t lane, uint64_t attempt,
+                                                 uint64_t k)
+{
+    uint64_t z = seed + (((lane << 24) | (attempt << 4) | k) + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ double unit53(uint64_t x) { return (double)(x >> 11) * 0x1.0p-53; }
+
+__device__ __forceinline__ double uniform(const double rg[2], uint64_t x)
+{
+    return rg[0] + (rg[1] - rg[0]) * unit53(x);
+}
+
+struct InitArgs {
+    malbec_ic_spec spec;
+    const int32_t *st_of_lane;
+    int64_t n;
+    double *state;
+    double *consts;
+    int64_t *attempts;
+};
+
+// Inverse-metric pieces at (r, theta): g^tt, g^tphi, g^phiphi, g^rr, g^thth.
+__device__ __forceinline__ void inverse_metric(double M, double a, double r, double s, double c,
+                                               double &itt, double &itp, double &ipp, double &irr,
+                                               double &ithth)
+{
+    const double a2 = a * a, s2 = s * s, r2 = r * r;
+    const double rho2 = r2 + a2 * c * c;
+    const double Delta = r2 - 2.0 * M * r + a2;
+    const double Sigma = (r2 + a2) * (r2 + a2) - a2 * Delta * s2;
+    const double den = rho2 * Delta;
+    itt = -Sigma / den;
+    itp = -2.0 * M * a * r / den;
+    ipp = (Delta - a2 * s2) / (den * s2);
+    irr = Delta / rho2;
+    ithth = 1.0 / rho2;
+}
+
+// 4-velocity from the constants of motion (Carter): with P = E (r^2 + a^2) - a L_z,
+// rho^2 u^r = s_r sqrt(R), rho^2 u^theta = s_th sqrt(Theta),
+// rho^2 u^t = (r^2 + a^2) P / Delta + a (L_z - a E sin^2),
+// rho^2 u^phi = a P / Delta + L_z / sin^2 - a E.
+__device__ __forceinline__ void velocity(double M, double a, double E, double Lz, double Q,
+                                         double mu2, double r, double s, double c, double sr,
+                                         double sth, double R, double Th, double u[4])
+{
+    const double a2 = a * a, s2 = s * s, r2 = r * r;
+    const double rho2 = r2 + a2 * c * c;
+    const double Delta = r2 - 2.0 * M * r + a2;
+    const double P = E * (r2 + a2) - a * Lz;
+    (void)mu2;
+    (void)Q;
+    u[0] = ((r2 + a2) * P / Delta + a * (Lz - a * E * s2)) / rho2;
+    u[1] = sr * sqrt(fmax(R, 0.0)) / rho2;
+    u[2] = sth * sqrt(fmax(Th, 0.0)) / rho2;
+    u[3] = (a * P / Delta + Lz / s2 - a * E) / rho2;
+}
+
+__device__ __forceinline__ double radial_potential(double M, double a, double E, double Lz, double Q,
+                                                   double mu2, double r)
+{
+    const double a2 = a * a, r2 = r * r;
+    const double P = E * (r2 + a2) - a * Lz;
+    const double Delta = r2 - 2.0 * M * r + a2;
+    const double L = Lz - a * E;
+    return P * P - Delta * (mu2 * r2 + L * L + Q);
+}
+
+__device__ __forceinline__ double polar_potential(double a, double E, double Lz, double Q, double mu2,
+                                                  double s, double c)
+{
+    return Q - c * c * (a * a * (mu2 - E * E) + Lz * Lz / (s * s));
+}
+
+__global__ void __launch_bounds__(256) init_kernel(InitArgs A, StTable T)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    int32_t sid = A.st_of_lane ? A.st_of_lane[i] : 0;
+    const bool bad_sid = sid < 0 || sid >= T.n_st;  // invalid index: NaN state
+    if (bad_sid) sid = 0;
+    const Spacetime S = T.st[sid];
+    const double M = S.M, a = S.a;
+    const malbec_ic_spec &P = A.spec;
+    const uint64_t lane = (uint64_t)(P.lane0 + i);
+    double y[8];
+    double cE = 0.0, cL = 0.0, cQ = 0.0, cmu2 = P.mu2;
+    int64_t used = 1;
+
+    if (P.mode == MALBEC_IC_CANONICAL) {
+        const double *z = P.rows + 8 * i;
+        double s, c;
+        sincos(z[2], &s, &c);
+        double itt, itp, ipp, irr, ithth;
+        inverse_metric(M, a, z[1], s, c, itt, itp, ipp, irr, ithth);
+        const double pt = -z[4];
+        y[0] = z[0]; y[1] = z[1]; y[2] = z[2]; y[3] = z[3];
+        y[4] = itt * pt + itp * z[7];
+        y[5] = irr * z[5];
+        y[6] = ithth * z[6];
+        y[7] = itp * pt + ipp * z[7];
+        cE = z[4];
+        cL = z[7];
+        cmu2 = 1.0;
+    } else if (P.mode == MALBEC_IC_CIRCULAR) {
+        const double rg[2] = {P.r_lo, P.r_hi};
+        const double r0 = uniform(rg, splitmix_out(P.seed, lane, 0, 0));
+        const double delta = P.dL * (2.0 * unit53(splitmix_out(P.seed, lane, 0, 1)) - 1.0);
+        // Bardeen-Press-Teukolsky circular orbit, upper sign prograde
+        const double sg = P.prograde ? 1.0 : -1.0;
+        const double sr = sqrt(r0), sM = sqrt(M);
+        const double den = pow(r0, 0.75) * sqrt(r0 * sr - 3.0 * M * sr + sg * 2.0 * a * sM);
+        const double Ec = (r0 * sr - 2.0 * M * sr + sg * a * sM) / den;
+        const double Lc = sg * sM * (r0 * r0 - sg * 2.0 * a * sM * sr + a * a) / den;
+        const double L = Lc * (1.0 + delta);
+        double itt, itp, ipp, irr, ithth;
+        inverse_metric(M, a, r0, 1.0, 0.0, itt, itp, ipp, irr, ithth);
+        double E = Ec;
+        if (P.e_from_norm) {
+            // g^{mu nu} p_mu p_nu = -1 with p = (-E, 0, 0, L): quadratic in E, g^tt < 0
+            const double qa = itt, qb = -2.0 * itp * L, qc = ipp * L * L + 1.0;
+            E = (-qb - sqrt(qb * qb - 4.0 * qa * qc)) / (2.0 * qa);
+        }
+        y[0] = 0.0; y[1] = r0; y[2] = 1.57079632679489661923; y[3] = 0.0;
+        y[4] = itt * (-E) + itp * L;
+        y[5] = 0.0;
+        y[6] = 0.0;
+        y[7] = itp * (-E) + ipp * L;
+        cE = E;
+        cL = L;
+        cQ = 0.0;
+        cmu2 = 1.0;
+    } else {
+        bool ok = false;
+        int64_t att = 0;
+        double r0 = 0, th0 = 0, sr = 1, sth = 1, R = 0, Th = 0, s = 0, c = 0;
+        for (att = 0; att < P.max_attempts; ++att) {
+            r0 = uniform(P.r_range, splitmix_out(P.seed, lane, att, 0));
+            th0 = uniform(P.th_range, splitmix_out(P.seed, lane, att, 1));
+            cE = uniform(P.E_range, splitmix_out(P.seed, lane, att, 2));
+            cL = uniform(P.Lz_range, splitmix_out(P.seed, lane, att, 3));
+            cQ = uniform(P.Q_range, splitmix_out(P.seed, lane, att, 4));
+            sr = (splitmix_out(P.seed, lane, att, 5) >> 63) ? -1.0 : 1.0;
+            sth = (splitmix_out(P.seed, lane, att, 6) >> 63) ? -1.0 : 1.0;
+            sincos(th0, &s, &c);
+            R = radial_potential(M, a, cE, cL, cQ, P.mu2, r0);
+            Th = polar_potential(a, cE, cL, cQ, P.mu2, s, c);
+            if (R >= 0.0 && Th >= 0.0) { ok = true; break; }
+        }
+        if (ok) {
+            y[0] = 0.0; y[1] = r0; y[2] = th0; y[3] = 0.0;
+            velocity(M, a, cE, cL, cQ, P.mu2, r0, s, c, sr, sth, R, Th, y + 4);
+            used = att + 1;
+        } else {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) y[k] = __builtin_nan("");
+            used = P.max_attempts;
+        }
+    }
+    if (bad_sid) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) y[k] = __builtin_nan("");
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) A.state[k * A.n + i] = y[k];
+    if (A.consts) {
+        A.consts[0 * A.n + i] = cE;
+        A.consts[1 * A.n + i] = cL;
+        A.consts[2 * A.n + i] = cQ;
+        A.consts[3 * A.n + i] = cmu2;
+    }
+    if (A.attempts) A.attempts[i] = used;
+}
+
+}  // namespace
+
+int launch_init(const malbec_ic_spec &spec, const StTable &T, const int32_t *st_of_lane, int64_t n,
+                double *state, double *consts, int64_t *attempts, hipStream_t s)
+{
+    InitArgs A;
+    A.spec = spec;
+    A.st_of_lane = T.n_st > 1 ? st_of_lane : nullptr;
+    A.n = n;
+    A.state = state;
+    A.consts = consts;
+    A.attempts = attempts;
+    const int block = 256;
+    hipLaunchKernelGGL(init_kernel, dim3(grid_for(n, block)), dim3(block), 0, s, A, T);
+    MALBEC_LAUNCH_CHECK("init_kernel");
+    return MALBEC_OK;
+}
+
+}  // namespace malbec

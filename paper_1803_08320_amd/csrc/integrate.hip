@@ -1,0 +1,142 @@
+// FP64 fixed-step RK4 integrator: one lane (thread) per geodesic.
+//
+// Each lane loads its 8-component state once (coalesced, component-major), runs
+// the steps of the launch with all stage values in registers and stores the state
+// once.  The only global traffic is 64 B in + 64 B out + status/steps per lane per
+// launch; the work is FP64 VALU arithmetic.  Spacetime constants come from the
+// kernel arguments (uniform batch) or from an LDS copy of the table (mixed batch).
+#include "internal.hpp"
+
+namespace malbec {
+
+namespace {
+
+struct IntArgs {
+    int64_t n;
+    double *state;
+    int32_t *status;
+    int32_t *steps;
+    const int32_t *st_of_lane;
+    double *ckpt;      // checkpoint slots or nullptr
+    double h;
+    double r_escape;
+    int32_t n_steps;   // steps in this launch
+    int32_t k0;        // index of this launch's first step within the call
+    int32_t ck_every;  // K (0 = none)
+    int32_t ck_last;   // index of the last slot of the call
+};
+
+__device__ __forceinline__ void put_slot(const IntArgs &A, int64_t i, int32_t slot, const double y[8])
+{
+    double *base = A.ckpt + (int64_t)slot * 8 * A.n;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) base[k * A.n + i] = y[k];
+}
+
+template <bool MULTI, bool CKPT>
+__global__ void __launch_bounds__(256) rk4_f64_kernel(IntArgs A, StTable T)
+{
+    __shared__ Spacetime lds_st[kMaxSt];
+    if (MULTI) {
+        for (int k = threadIdx.x; k < T.n_st; k += blockDim.x) lds_st[k] = T.st[k];
+        __syncthreads();
+    }
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    int32_t st = A.status[i];
+    int32_t sid = 0;
+    if (MULTI) {
+        sid = A.st_of_lane[i];
+        if (sid < 0 || sid >= T.n_st) {  // invalid spacetime index: the lane cannot step
+            sid = 0;
+            if (st == kActive) st = kNonfinite;
+            A.status[i] = st;
+        }
+    }
+    const Spacetime S = MULTI ? lds_st[sid] : T.st[0];
+
+    double y[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) y[k] = A.state[k * A.n + i];
+    int32_t taken = 0;
+    int32_t next_slot = 0;
+    if (CKPT) next_slot = (A.k0 + A.ck_every - 1) / A.ck_every;  // first slot at or after k0
+
+    if (st == kActive) {
+        for (int32_t k = 0; k < A.n_steps; ++k) {
+            if (CKPT && (A.k0 + k) == next_slot * A.ck_every) {
+                put_slot(A, i, next_slot, y);
+                ++next_slot;
+            }
+            double y1[8], sr[3];
+            rk4_step_f64(S, A.h, y, y1, sr);
+            ++taken;
+            bool accept;
+            st = terminate_f64(S, A.r_escape, sr, y1, accept);
+            if (accept) {
+#pragma unroll
+                for (int c = 0; c < 8; ++c) y[c] = y1[c];
+            }
+            if (st != kActive) break;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) A.state[k * A.n + i] = y[k];
+        A.status[i] = st;
+        A.steps[i] += taken;
+    }
+    if (CKPT) {
+        // slots up to the end of this launch (inclusive of the call's last slot when
+        // this launch ends the call) repeat the current state for stopped lanes and
+        // receive the end state otherwise
+        const int32_t end = A.k0 + A.n_steps;
+        int32_t last = end / A.ck_every;
+        if (last * A.ck_every == end && last != A.ck_last) --last;  // next launch writes it
+        for (int32_t s = next_slot; s <= last; ++s) put_slot(A, i, s, y);
+    }
+}
+
+template <bool MULTI, bool CKPT>
+int launch_kernel(const IntArgs &A, const StTable &T, int block, hipStream_t s)
+{
+    hipLaunchKernelGGL((rk4_f64_kernel<MULTI, CKPT>), dim3(grid_for(A.n, block)), dim3(block), 0, s,
+                       A, T);
+    MALBEC_LAUNCH_CHECK("rk4_f64_kernel");
+    return MALBEC_OK;
+}
+
+}  // namespace
+
+int launch_integrate_f64(const malbec_run &run, const StTable &T, const int32_t *st_of_lane,
+                         int64_t n, double *state, int32_t *status, int32_t *steps,
+                         double *checkpoints, hipStream_t s)
+{
+    const int block = run.block > 0 ? run.block : 256;
+    if (block > 256) return fail(MALBEC_EINVAL, "block %d exceeds the kernel's launch bound 256", block);
+    const bool multi = st_of_lane != nullptr && T.n_st > 1;
+    const int64_t total = run.n_steps;
+    const int64_t chunk = run.steps_per_chunk > 0 ? run.steps_per_chunk : total;
+    IntArgs A;
+    A.n = n;
+    A.state = state;
+    A.status = status;
+    A.steps = steps;
+    A.st_of_lane = multi ? st_of_lane : nullptr;
+    A.ckpt = run.checkpoint_every > 0 ? checkpoints : nullptr;
+    A.h = run.h;
+    A.r_escape = run.r_escape;
+    A.ck_every = run.checkpoint_every;
+    A.ck_last = run.checkpoint_every > 0 ? (int32_t)(total / run.checkpoint_every) : 0;
+    for (int64_t k0 = 0; k0 < total; k0 += chunk) {
+        A.k0 = (int32_t)k0;
+        A.n_steps = (int32_t)((total - k0) < chunk ? (total - k0) : chunk);
+        int rc;
+        if (A.ckpt)
+            rc = multi ? launch_kernel<true, true>(A, T, block, s) : launch_kernel<false, true>(A, T, block, s);
+        else
+            rc = multi ? launch_kernel<true, false>(A, T, block, s) : launch_kernel<false, false>(A, T, block, s);
+        if (rc) return rc;
+    }
+    return MALBEC_OK;
+}
+
+}  // namespace malbec

@@ -1,0 +1,60 @@
+// Internal host-side declarations shared by the translation units of libmalbec.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/malbec.h"
+#include "kerr_device.hpp"
+
+namespace malbec {
+
+// Records the error text for malbec_last_error() and returns `code`.
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+void clear_error();
+
+#define MALBEC_HIP_CHECK(expr)                                                              \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return ::malbec::fail(MALBEC_EDEVICE, "%s failed: %s", #expr,                   \
+                                  hipGetErrorString(e_));                                   \
+    } while (0)
+
+#define MALBEC_LAUNCH_CHECK(name)                                                           \
+    do {                                                                                    \
+        hipError_t e_ = hipGetLastError();                                                  \
+        if (e_ != hipSuccess)                                                               \
+            return ::malbec::fail(MALBEC_EDEVICE, "launch of %s failed: %s", name,          \
+                                  hipGetErrorString(e_));                                   \
+    } while (0)
+
+constexpr int kMaxSt = MALBEC_MAX_SPACETIMES;
+
+// Spacetime table passed by value in kernel arguments.
+struct StTable {
+    Spacetime st[kMaxSt];
+    int32_t n_st;
+};
+
+// Validates a batch and fills the table (r_stop from horizon_factor, r_zone from
+// zone_factor).  Returns MALBEC_OK or an error code with the text recorded.
+int make_table(const malbec_batch *b, double horizon_factor, double zone_factor, StTable &T);
+
+// Launchers (one per translation unit).  Arguments are validated by the caller.
+int launch_init(const malbec_ic_spec &spec, const StTable &T, const int32_t *st_of_lane,
+                int64_t n, double *state, double *consts, int64_t *attempts, hipStream_t s);
+int launch_integrate_f64(const malbec_run &run, const StTable &T, const int32_t *st_of_lane,
+                         int64_t n, double *state, int32_t *status, int32_t *steps,
+                         double *checkpoints, hipStream_t s);
+int launch_integrate_f32k(const malbec_run &run, const StTable &T, const int32_t *st_of_lane,
+                          int64_t n, double *state, int32_t *status, int32_t *steps,
+                          hipStream_t s);
+int launch_camera(const malbec_camera &cam, double r_stop, double disk_r_in, int32_t *status,
+                  int32_t *steps, double *hit, double *final_state, void *ws, hipStream_t s);
+int launch_invariants(const StTable &T, const int32_t *st_of_lane, int64_t n,
+                      const double *state, double *out, hipStream_t s);
+
+inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
+
+}  // namespace malbec

@@ -1,0 +1,63 @@
+// Invariant monitor: (E, L_z, Carter Q, g(u,u)) of each lane in FP64.
+//   E   = -(g_tt u^t + g_tphi u^phi)            (conserved: dp_t/dtau = 0, Sections 3-4)
+//   L_z = g_tphi u^t + g_phiphi u^phi           (conserved: dp_phi/dtau = 0)
+//   Q   = (rho^2 u^theta)^2 + cos^2 [a^2 (mu^2 - E^2) + L_z^2 / sin^2],  mu^2 = -g(u,u)
+//   g(u,u) = -1 timelike (Section 2, eq. geo), 0 null.
+#include "internal.hpp"
+
+namespace malbec {
+
+namespace {
+
+__global__ void __launch_bounds__(256) invariants_kernel(const double *__restrict__ state,
+                                                         double *__restrict__ out,
+                                                         const int32_t *__restrict__ st_of_lane,
+                                                         int64_t n, StTable T)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t sid = st_of_lane ? st_of_lane[i] : 0;
+    if (sid < 0 || sid >= T.n_st) {  // invalid spacetime index
+        for (int k = 0; k < 4; ++k) out[k * n + i] = __builtin_nan("");
+        return;
+    }
+    const Spacetime S = T.st[sid];
+    const double M = S.M, a = S.a;
+    const double r = state[1 * n + i], th = state[2 * n + i];
+    const double ut = state[4 * n + i], ur = state[5 * n + i];
+    const double uth = state[6 * n + i], uph = state[7 * n + i];
+    double s, c;
+    sincos(th, &s, &c);
+    const double a2 = a * a, s2 = s * s, r2 = r * r;
+    const double rho2 = r2 + a2 * c * c;
+    const double Delta = r2 - 2.0 * M * r + a2;
+    const double q = 2.0 * M * r / rho2;
+    const double gtt = q - 1.0;
+    const double gtp = -a * q * s2;
+    const double gpp = (r2 + a2 + a2 * q * s2) * s2;
+    const double grr = rho2 / Delta;
+    const double norm = gtt * ut * ut + 2.0 * gtp * ut * uph + gpp * uph * uph + grr * ur * ur +
+                        rho2 * uth * uth;
+    const double E = -(gtt * ut + gtp * uph);
+    const double Lz = gtp * ut + gpp * uph;
+    const double pth = rho2 * uth;
+    const double Q = pth * pth + c * c * (a2 * (-norm - E * E) + Lz * Lz / s2);
+    out[0 * n + i] = E;
+    out[1 * n + i] = Lz;
+    out[2 * n + i] = Q;
+    out[3 * n + i] = norm;
+}
+
+}  // namespace
+
+int launch_invariants(const StTable &T, const int32_t *st_of_lane, int64_t n, const double *state,
+                      double *out, hipStream_t s)
+{
+    const int block = 256;
+    hipLaunchKernelGGL(invariants_kernel, dim3(grid_for(n, block)), dim3(block), 0, s, state, out,
+                       T.n_st > 1 ? st_of_lane : nullptr, n, T);
+    MALBEC_LAUNCH_CHECK("invariants_kernel");
+    return MALBEC_OK;
+}
+
+}  // namespace malbec

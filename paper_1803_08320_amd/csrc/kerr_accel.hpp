@@ -1,0 +1,150 @@
+// Geodesic acceleration of the Kerr metric, shared by the FP64 and FP32 kernels.
+//
+// Kerr metric in Boyer-Lindquist coordinates (Quiroga, MALBEC, Section 2,
+// eq. kerr).  The geodesic acceleration du^mu/dtau = -Gamma^mu_ab u^a u^b is
+// not formed from the 40 Christoffel symbols.  It uses the identity
+//     g_{mu nu} du^nu/dtau = 1/2 (d_mu g_ab) u^a u^b - (d_l g_{mu b}) u^l u^b,
+// which is the Christoffel contraction with the metric lowered, and then raises
+// the index with the block-diagonal inverse metric ((t, phi) 2x2 block,
+// g^rr = Delta / rho^2, g^thth = 1 / rho^2).  Only r and theta partials of the 5
+// nonzero metric components enter.  Everything stays in registers.
+//
+// With q = 2 M r / rho^2:
+//   g_tt = q - 1,  g_tphi = -a q s^2,  g_phiphi = (r^2 + a^2 + a^2 q s^2) s^2,
+//   g_rr = rho^2 / Delta,  g_thth = rho^2,
+// and det of the (t, phi) block = -Delta s^2.  One reciprocal 1 / (rho^2 Delta s^2)
+// yields 1/rho^2, 1/Delta and 1/(Delta s^2).
+#pragma once
+
+#if defined(__HIPCC__)
+#define MALBEC_HD __host__ __device__
+#else
+#define MALBEC_HD
+#include <cmath>
+using std::fma;
+#endif
+
+namespace malbec {
+
+// du^mu/dtau for the 4-velocity (ut, ur, uth, uph) at (r, theta) with s = sin theta,
+// c = cos theta.  T = double or float.
+template <typename T>
+MALBEC_HD inline void kerr_accel(T M, T a, T r, T s, T c, T ut, T ur, T uth, T uph,
+                                           T &at, T &ar, T &ath, T &aph)
+{
+    const T a2 = a * a;
+    const T s2 = s * s;
+    const T sc = s * c;
+    const T r2 = r * r;
+    const T rho2 = fma(a2, c * c, r2);
+    const T Delta = fma(r, r - T(2) * M, a2);
+    const T inv = T(1) / (rho2 * Delta * s2);
+    const T iDs2 = inv * rho2;        // 1 / (Delta s^2)
+    const T irho2 = inv * (Delta * s2); // 1 / rho^2
+    const T iDelta = iDs2 * s2;       // 1 / Delta
+
+    const T q = T(2) * M * r * irho2;
+    const T gtt = q - T(1);
+    const T gtp = -a * q * s2;
+    const T A = r2 + a2;
+    const T gpp = fma(a2 * q, s2, A) * s2;
+
+    // partial derivatives of q
+    const T dq_r = T(2) * M * irho2 * fma(T(-2) * r2, irho2, T(1));
+    const T twosc = T(2) * sc;
+    const T dq_th = q * a2 * twosc * irho2;
+    // d(q s^2)/dtheta
+    const T dqs2_th = fma(dq_th, s2, q * twosc);
+
+    const T dgtt_r = dq_r, dgtt_th = dq_th;
+    const T dgtp_r = -a * s2 * dq_r;
+    const T dgtp_th = -a * dqs2_th;
+    const T dgpp_r = fma(a2 * s2, dq_r, T(2) * r) * s2;
+    const T dgpp_th = fma(a2 * dqs2_th, s2, fma(a2 * q, s2, A) * twosc);
+    const T grr = rho2 * iDelta;
+    const T dgrr_r = iDelta * fma(-grr, T(2) * (r - M), T(2) * r);
+    const T dgrr_th = -a2 * twosc * iDelta;
+
+    // (d_l g_{t b}) u^b and (d_l g_{phi b}) u^b for l = r, theta
+    const T Pt_r = fma(dgtt_r, ut, dgtp_r * uph);
+    const T Pt_th = fma(dgtt_th, ut, dgtp_th * uph);
+    const T Pp_r = fma(dgtp_r, ut, dgpp_r * uph);
+    const T Pp_th = fma(dgtp_th, ut, dgpp_th * uph);
+
+    // lowered acceleration components F_mu = g_{mu nu} du^nu/dtau
+    const T Wt = fma(ur, Pt_r, uth * Pt_th);   // F_t = -Wt
+    const T Wp = fma(ur, Pp_r, uth * Pp_th);   // F_phi = -Wp
+    const T Qr = fma(ut, Pt_r, uph * Pp_r);    // (t,phi) part of (d_r g_ab) u^a u^b
+    const T Qth = fma(ut, Pt_th, uph * Pp_th); // (t,phi) part of (d_th g_ab) u^a u^b
+    const T urur = ur * ur, uthuth = uth * uth, uruth = ur * uth;
+    // F_r = Qr/2 + r uth^2 - dgrr_r ur^2 / 2 - dgrr_th ur uth
+    const T Fr = fma(T(0.5), fma(-dgrr_r, urur, Qr), fma(r, uthuth, -dgrr_th * uruth));
+    // F_th = Qth/2 + dgrr_th ur^2 / 2 + a^2 s c uth^2 - 2 r ur uth
+    const T Fth = fma(T(0.5), fma(dgrr_th, urur, Qth), fma(a2 * sc, uthuth, T(-2) * r * uruth));
+
+    // raise: (t, phi) block inverse = (1 / (-Delta s^2)) [[g_pp, -g_tp], [-g_tp, g_tt]]
+    at = iDs2 * fma(gpp, Wt, -gtp * Wp);
+    aph = iDs2 * fma(gtt, Wp, -gtp * Wt);
+    ar = Fr * Delta * irho2;
+    ath = Fth * irho2;
+}
+
+// One classic RK4 step (b = 1/6, 1/3, 1/3, 1/6; c = 0, 1/2, 1/2, 1) of all 8
+// components; accel(r, th, ut, ur, uth, uph, at, ar, ath, aph) evaluates du/dtau.  The right-hand side does not depend on t or phi, so only
+// (r, theta, u) are formed at the stage points; t and phi accumulate the stage
+// values of u^t and u^phi with the same weights.  sr[] receives the radii of the
+// three intermediate stage points.
+template <typename T, typename Accel>
+MALBEC_HD inline void rk4_step(const Accel &accel, T h, const T y[8], T y1[8], T sr[3])
+{
+    const T hh = T(0.5) * h;
+    T at, ar, ath, aph;
+    T acc[8];
+    T s1, s2, s3, s4, s5, s6; // stage point (r, th, ut, ur, uth, uph)
+
+    // k1 = f(y)
+    accel(y[1], y[2], y[4], y[5], y[6], y[7], at, ar, ath, aph);
+    acc[0] = y[4]; acc[1] = y[5]; acc[2] = y[6]; acc[3] = y[7];
+    acc[4] = at; acc[5] = ar; acc[6] = ath; acc[7] = aph;
+    s1 = fma(hh, y[5], y[1]); s2 = fma(hh, y[6], y[2]);
+    s3 = fma(hh, at, y[4]); s4 = fma(hh, ar, y[5]); s5 = fma(hh, ath, y[6]); s6 = fma(hh, aph, y[7]);
+    sr[0] = s1;
+
+    // k2 = f(y + h/2 k1)
+    accel(s1, s2, s3, s4, s5, s6, at, ar, ath, aph);
+    acc[0] = fma(T(2), s3, acc[0]); acc[1] = fma(T(2), s4, acc[1]);
+    acc[2] = fma(T(2), s5, acc[2]); acc[3] = fma(T(2), s6, acc[3]);
+    acc[4] = fma(T(2), at, acc[4]); acc[5] = fma(T(2), ar, acc[5]);
+    acc[6] = fma(T(2), ath, acc[6]); acc[7] = fma(T(2), aph, acc[7]);
+    {
+        T n1 = fma(hh, s4, y[1]), n2 = fma(hh, s5, y[2]);
+        T n3 = fma(hh, at, y[4]), n4 = fma(hh, ar, y[5]), n5 = fma(hh, ath, y[6]), n6 = fma(hh, aph, y[7]);
+        s1 = n1; s2 = n2; s3 = n3; s4 = n4; s5 = n5; s6 = n6;
+    }
+    sr[1] = s1;
+
+    // k3 = f(y + h/2 k2)
+    accel(s1, s2, s3, s4, s5, s6, at, ar, ath, aph);
+    acc[0] = fma(T(2), s3, acc[0]); acc[1] = fma(T(2), s4, acc[1]);
+    acc[2] = fma(T(2), s5, acc[2]); acc[3] = fma(T(2), s6, acc[3]);
+    acc[4] = fma(T(2), at, acc[4]); acc[5] = fma(T(2), ar, acc[5]);
+    acc[6] = fma(T(2), ath, acc[6]); acc[7] = fma(T(2), aph, acc[7]);
+    {
+        T n1 = fma(h, s4, y[1]), n2 = fma(h, s5, y[2]);
+        T n3 = fma(h, at, y[4]), n4 = fma(h, ar, y[5]), n5 = fma(h, ath, y[6]), n6 = fma(h, aph, y[7]);
+        s1 = n1; s2 = n2; s3 = n3; s4 = n4; s5 = n5; s6 = n6;
+    }
+    sr[2] = s1;
+
+    // k4 = f(y + h k3)
+    accel(s1, s2, s3, s4, s5, s6, at, ar, ath, aph);
+    acc[0] += s3; acc[1] += s4; acc[2] += s5; acc[3] += s6;
+    acc[4] += at; acc[5] += ar; acc[6] += ath; acc[7] += aph;
+
+    const T h6 = h * T(1.0 / 6.0);
+    // acc[0..3] hold the weighted sums of (u^t, u^r, u^theta, u^phi) = dx/dtau
+#pragma unroll
+    for (int k = 0; k < 8; ++k) y1[k] = fma(h6, acc[k], y[k]);
+}
+
+}  // namespace malbec

@@ -1,0 +1,164 @@
+"""C ABI checks that need no GPU: the library loads, exports every symbol that
+include/malbec.h declares, its structures have the header's layout, and argument
+errors are reported without touching the device."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+from conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "malbec.h")
+
+
+@pytest.fixture(scope="module")
+def m():
+    import paper_1803_08320_amd as m
+    if not os.path.exists(m.LIB_PATH):
+        from paper_1803_08320_amd import _build_lib
+        _build_lib.build()
+    m.lib()
+    return m
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"MALBEC_API\s+[\w\s\*]*?\b(malbec_\w+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(m):
+    names = declared_functions()
+    assert len(names) >= 7
+    out = subprocess.run(["nm", "-D", "--defined-only", m.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (malbec_\w+)", out))
+    assert set(names) <= exported, set(names) - exported
+    for name in names:
+        assert hasattr(m.lib(), name)
+    assert set(names) == set(m.EXPORTS)
+    # internal C++ symbols stay hidden
+    assert not re.search(r"\bT _ZN6malbec", out)
+
+
+def test_struct_layout_matches_header(m, tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "malbec.h"\n'
+                   "#define P(T) printf(#T \" %zu\\n\", sizeof(T));\n"
+                   "#define O(T, f) printf(#T \".\" #f \" %zu\\n\", offsetof(T, f));\n"
+                   "int main(void){P(malbec_spacetime)P(malbec_batch)P(malbec_ic_spec)"
+                   "P(malbec_run)P(malbec_camera)O(malbec_ic_spec, rows)O(malbec_ic_spec, max_attempts)"
+                   "O(malbec_run, checkpoint_every)O(malbec_camera, max_steps)O(malbec_camera, persistent)"
+                   "O(malbec_batch, st_of_lane)return 0;}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    lines = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = dict(l.rsplit(" ", 1) for l in lines if l)
+    assert int(got["malbec_spacetime"]) == C.sizeof(m.c_spacetime)
+    assert int(got["malbec_batch"]) == C.sizeof(m.c_batch)
+    assert int(got["malbec_ic_spec"]) == C.sizeof(m.c_ic_spec)
+    assert int(got["malbec_run"]) == C.sizeof(m.c_run)
+    assert int(got["malbec_camera"]) == C.sizeof(m.c_camera)
+    assert int(got["malbec_ic_spec.rows"]) == m.c_ic_spec.rows.offset
+    assert int(got["malbec_ic_spec.max_attempts"]) == m.c_ic_spec.max_attempts.offset
+    assert int(got["malbec_run.checkpoint_every"]) == m.c_run.checkpoint_every.offset
+    assert int(got["malbec_camera.max_steps"]) == m.c_camera.max_steps.offset
+    assert int(got["malbec_camera.persistent"]) == m.c_camera.persistent.offset
+    assert int(got["malbec_batch.st_of_lane"]) == m.c_batch.st_of_lane.offset
+
+
+def _batch(m, sts=((1.0, 0.9),)):
+    arr = (m.c_spacetime * len(sts))(*[m.c_spacetime(M, a) for M, a in sts])
+    return arr, m.c_batch(C.cast(arr, C.POINTER(m.c_spacetime)), len(sts), 0, None)
+
+
+def _run(m, **kw):
+    d = dict(h=0.02, n_steps=10, precision=0, block=0, horizon_factor=1.01, r_escape=1500.0,
+             fp64_zone_factor=1.2, steps_per_chunk=0, checkpoint_every=0)
+    d.update(kw)
+    return m.c_run(**d)
+
+
+FAKE = C.c_void_p(0x1000)  # never dereferenced: every case below fails validation first
+
+
+@pytest.mark.parametrize("kw,sts,n,expect", [
+    (dict(h=0.0), ((1.0, 0.9),), 4, -1),
+    (dict(h=float("nan")), ((1.0, 0.9),), 4, -1),
+    (dict(n_steps=-1), ((1.0, 0.9),), 4, -1),
+    (dict(), ((1.0, 1.2),), 4, -1),          # a > M
+    (dict(), ((0.0, 0.0),), 4, -1),          # M <= 0
+    (dict(), ((1.0, -0.1),), 4, -1),         # a < 0
+    (dict(horizon_factor=0.5), ((1.0, 0.9),), 4, -1),
+    (dict(precision=7), ((1.0, 0.9),), 4, -1),
+    (dict(block=100), ((1.0, 0.9),), 4, -1),
+    (dict(), ((1.0, 0.9),), -3, -1),         # n < 0
+    (dict(checkpoint_every=4), ((1.0, 0.9),), 4, -1),  # no checkpoint buffer
+])
+def test_integrate_argument_errors(m, kw, sts, n, expect):
+    run = _run(m, **kw)
+    arr, b = _batch(m, sts)
+    rc = m.lib().malbec_integrate(C.byref(run), C.byref(b), n, FAKE, FAKE, FAKE, None, None, 0, None)
+    assert rc == expect
+    assert m.last_error() != ""
+
+
+def test_null_pointer_and_table_errors(m):
+    run = _run(m)
+    arr, b = _batch(m)
+    assert m.lib().malbec_integrate(C.byref(run), C.byref(b), 4, None, FAKE, FAKE, None, None, 0,
+                                    None) == -1
+    assert "non-NULL" in m.last_error()
+    assert m.lib().malbec_integrate(None, C.byref(b), 4, FAKE, FAKE, FAKE, None, None, 0, None) == -1
+    assert m.lib().malbec_integrate(C.byref(run), None, 4, FAKE, FAKE, FAKE, None, None, 0, None) == -1
+    big = [(1.0, 0.1)] * 65
+    arr, b = _batch(m, big)
+    assert m.lib().malbec_integrate(C.byref(run), C.byref(b), 4, FAKE, FAKE, FAKE, None, None, 0,
+                                    None) == -1
+    assert "n_st" in m.last_error()
+    # zero lanes or zero steps: a valid no-op that enqueues nothing
+    arr, b = _batch(m)
+    assert m.lib().malbec_integrate(C.byref(run), C.byref(b), 0, None, None, None, None, None, 0,
+                                    None) == 0
+    assert m.last_error() == ""
+    run0 = _run(m, n_steps=0)
+    assert m.lib().malbec_integrate(C.byref(run0), C.byref(b), 4, FAKE, FAKE, FAKE, None, None, 0,
+                                    None) == 0
+
+
+def test_init_and_camera_argument_errors(m):
+    arr, b = _batch(m)
+    spec = m.ICSpec(mode=9).to_c(4)
+    assert m.lib().malbec_init_particles(C.byref(spec), C.byref(b), 4, FAKE, None, None, None) == -1
+    spec = m.ICSpec(mode=m.IC_CONSTANTS, max_attempts=0).to_c(4)
+    assert m.lib().malbec_init_particles(C.byref(spec), C.byref(b), 4, FAKE, None, None, None) == -1
+    spec = m.ICSpec(mode=m.IC_CONSTANTS, E_range=(1.0, 0.5)).to_c(4)
+    assert m.lib().malbec_init_particles(C.byref(spec), C.byref(b), 4, FAKE, None, None, None) == -1
+    spec = m.ICSpec(mode=m.IC_CANONICAL).to_c(4)
+    assert m.lib().malbec_init_particles(C.byref(spec), C.byref(b), 4, FAKE, None, None, None) == -1
+    cam = m.Camera(nx=4, ny=4).to_c()
+    ws_need = m.workspace_bytes(m.OP_CAMERA, 16)
+    assert ws_need >= 8
+    # workspace too small
+    assert m.lib().malbec_trace_camera(C.byref(cam), FAKE, FAKE, FAKE, None, FAKE, 4, None) == -2
+    for bad in (dict(a=1.5), dict(incl=0.0), dict(nx=0), dict(h0=-1.0), dict(r_escape=10.0),
+                dict(max_steps=0), dict(block=96)):
+        kw = dict(nx=4, ny=4)
+        kw.update(bad)
+        cam = m.Camera(**kw).to_c()
+        assert m.lib().malbec_trace_camera(C.byref(cam), FAKE, FAKE, FAKE, None, FAKE, ws_need,
+                                           None) == -1, bad
+    assert m.lib().malbec_invariants(C.byref(b), -1, FAKE, FAKE, None) == -1
+    assert m.version() >= 300
+
+
+def test_flop_count_constant(m, tmp_path):
+    """The roofline's flops per lane-step equal the static count of the templates the
+    kernels instantiate."""
+    exe = tmp_path / "flopcount"
+    src = os.path.join(ROOT, "paper_1803_08320_amd", "csrc", "flopcount.cpp")
+    subprocess.run(["g++", "-O0", "-std=c++17", src, "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
+    vals = dict(l.split() for l in out.strip().split("\n"))
+    assert int(vals["step_flops"]) == m.FLOPS_PER_STEP_F64
