@@ -71,11 +71,14 @@ extern "C" {
 #define MALBEC_IC_CANONICAL 0 /* the paper's initial-condition rows (Section 5 table) */
 #define MALBEC_IC_CIRCULAR 1  /* equatorial near-circular orbits (Sections 3-4) */
 #define MALBEC_IC_CONSTANTS 2 /* random (E, L_z, Carter Q) with potential rejection */
+#define MALBEC_IC_PARAMS 3    /* rows (r0, theta0, u^r0, u^theta0, L_z, E): the map the
+                                 adjoint differentiates */
 
 #define MALBEC_MAX_SPACETIMES 64
 
 #define MALBEC_OP_INTEGRATE 1
 #define MALBEC_OP_CAMERA 2
+#define MALBEC_OP_ADJOINT 3
 
 /* One Kerr spacetime: mass M > 0 and spin a in [0, M] (Section 2; a > M is a naked
  * singularity and is rejected). */
@@ -109,7 +112,10 @@ typedef struct {
     double r_range[2], th_range[2], E_range[2], Lz_range[2], Q_range[2];
     int64_t max_attempts; /* lanes that exhaust it get NaN state and attempts = max_attempts */
     /* CANONICAL: device, n rows of 8 doubles (t, r, theta, phi, p_t, p_r, p_theta, p_phi),
-       row-major as in the paper's IC table, with the paper's sign p_t = +E. */
+       row-major as in the paper's IC table, with the paper's sign p_t = +E.
+       PARAMS: device, n rows of 6 doubles (r0, theta0, u^r0, u^theta0, L_z, E): state
+       (0, r0, theta0, 0, u^t, u^r0, u^theta0, u^phi) with (u^t, u^phi) = G^{-1} (-E, L_z),
+       G the (t, phi) block of the metric at (r0, theta0). */
     const double *rows;
 } malbec_ic_spec;
 
@@ -154,9 +160,10 @@ MALBEC_API const char *malbec_last_error(void);
 /* Library version as 10000 * major + 100 * minor + patch. */
 MALBEC_API int malbec_version(void);
 
-/* Bytes of caller workspace an operation needs: op = MALBEC_OP_INTEGRATE (n lanes) or
- * MALBEC_OP_CAMERA (n = nx * ny pixels).  Returns 0 for operations that need none. */
-MALBEC_API size_t malbec_workspace_bytes(int32_t op, int64_t n);
+/* Bytes of caller workspace an operation needs: op = MALBEC_OP_INTEGRATE (n lanes),
+ * MALBEC_OP_CAMERA (n = nx * ny pixels) or MALBEC_OP_ADJOINT (n lanes, aux = the
+ * checkpoint interval K: K * 8 * n doubles).  Returns 0 for operations that need none. */
+MALBEC_API size_t malbec_workspace_bytes(int32_t op, int64_t n, int32_t aux);
 
 /* Build the initial state of n lanes on the device (one GPU thread per lane).
  * spec: host.  b: host (st_of_lane device or NULL).  state: device, 8n doubles (out).
@@ -207,6 +214,25 @@ MALBEC_API int malbec_trace_camera(const malbec_camera *cam, int32_t *status, in
  * Errors: MALBEC_EINVAL, MALBEC_EDEVICE. */
 MALBEC_API int malbec_invariants(const malbec_batch *b, int64_t n, const double *state, double *out,
                       void *stream);
+
+/* Discrete adjoint of malbec_integrate (FP64): the exact gradient of the computed RK4
+ * map.  Inputs describe a forward call made with run->checkpoint_every = K > 0 that
+ * started with all lanes ACTIVE and steps = 0: checkpoints (device, (N/K + 1) * 8n),
+ * status and steps (device n, as that call left them), run (same h, n_steps = N, K,
+ * horizon_factor, r_escape, block).  g_final (device 8n) = dL/dy_N.
+ * Outputs: g_initial (device 8n) = dL/dy_0; g_named (device 5n, nullable) = dL/dp
+ * for p = (r0, theta0, u^r0, u^theta0, L_z) through the MALBEC_IC_PARAMS map with E
+ * held fixed (E_fixed: device n, nullable: E is then taken from the initial state).
+ * Steps a lane did not take (after it stopped, or a terminal step whose result was
+ * discarded) contribute the identity.  ws: caller workspace of
+ * malbec_workspace_bytes(MALBEC_OP_ADJOINT, n, K) bytes (recomputed segment states).
+ * There is no derivative in the paper; this is the transposed tangent of the RK4
+ * step of Section 5.  Errors: MALBEC_EINVAL, MALBEC_ENOMEM, MALBEC_EDEVICE. */
+MALBEC_API int malbec_adjoint(const malbec_run *run, const malbec_batch *b, int64_t n,
+                              const double *checkpoints, const int32_t *status,
+                              const int32_t *steps, const double *g_final, double *g_initial,
+                              const double *E_fixed, double *g_named, void *ws, size_t ws_bytes,
+                              void *stream);
 
 #ifdef __cplusplus
 }

@@ -88,7 +88,7 @@ def lib():
                                           P(i64), P(i32), P(i32), P(d), vp, C.c_int]),
         "oracle_ray_ic": (None, [d, d, d, d, d, d, P(d)]),
         "oracle_trace_rays": (C.c_int, [d, d, d, d, i64, P(d), P(d), d, d, d, d, d, d, i64,
-                                        P(i32), P(i32), P(d), C.c_int]),
+                                        P(i32), P(i32), P(d), vp, C.c_int]),
         "oracle_tangent": (None, [d, d, d, i64, P(d), P(d), vp, P(d)]),
         "oracle_ic_map": (None, [d, d, d, P(d), P(d)]),
         "oracle_grad_ic": (C.c_int, [d, d, d, i64, i64, P(d), P(d), P(d), P(d), vp, C.c_int]),
@@ -307,17 +307,23 @@ def ray_ic(M, a, r_obs, incl, alpha, beta):
 
 
 def trace_rays(M, a, r_obs, incl, alpha, beta, h0=0.1, h_r0=10.0, r_escape=1500.0,
-               horizon_factor=1.01, disk_r_in=1.0, disk_r_out=-1.0, max_steps=100000, nthreads=0):
-    """Trace rays at explicit image-plane points; disk_r_in > disk_r_out disables the disk."""
+               horizon_factor=1.01, disk_r_in=1.0, disk_r_out=-1.0, max_steps=100000, nthreads=0,
+               final_state=False):
+    """Trace rays at explicit image-plane points; disk_r_in > disk_r_out disables the disk.
+    Returns (status, steps, hit[2, n]) and, with final_state=True, the state [8, n] too."""
     alpha = _f64(alpha)
     beta = _f64(beta, alpha.size)
     n = alpha.size
     status = np.zeros(n, np.int32)
     steps = np.zeros(n, np.int32)
     hit = np.zeros(2 * n)
+    fs = np.zeros(8 * n) if final_state else None
     lib().oracle_trace_rays(M, a, r_obs, incl, n, _dp(alpha), _dp(beta), h0, h_r0, r_escape,
                             horizon_factor, disk_r_in, disk_r_out, max_steps, _ip(status),
-                            _ip(steps), _dp(hit), nthreads)
+                            _ip(steps), _dp(hit), None if fs is None else fs.ctypes.data_as(C.c_void_p),
+                            nthreads)
+    if final_state:
+        return status, steps, hit.reshape(n, 2).T.copy(), fs.reshape(8, n)
     return status, steps, hit.reshape(n, 2).T.copy()
 
 

@@ -591,7 +591,8 @@ int oracle_trace_camera(double M, double a, double r_obs, double incl, double ha
 int oracle_trace_rays(double M, double a, double r_obs, double incl, int64_t nray, const double *alpha,
                       const double *beta, double h0, double h_r0, double r_escape,
                       double horizon_factor, double disk_r_in, double disk_r_out, int64_t max_steps,
-                      int32_t *status, int32_t *steps, double *hit, int nthreads)
+                      int32_t *status, int32_t *steps, double *hit,
+                      double *final_state /* 8*nray SoA, nullable */, int nthreads)
 {
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
@@ -603,6 +604,7 @@ int oracle_trace_rays(double M, double a, double r_obs, double incl, int64_t nra
         oracle_ray_ic(M, a, r_obs, incl, alpha[q], beta[q], y);
         steps[q] = (int32_t)trace_ray(M, a, h0, h_r0, r_escape, rh, disk_r_in, disk_r_out, max_steps,
                                       y, &status[q], hit + 2 * q);
+        if (final_state) put_state(final_state, nray, q, y);
     }
     return 0;
 }

@@ -22,7 +22,8 @@ import torch  # noqa: F401  (loads the HIP runtime before libmalbec)
 
 __all__ = [
     "ICSpec", "Camera", "init_particles", "integrate", "invariants", "trace_camera",
-    "workspace_bytes", "last_error", "version", "lib", "MalbecError", "STATUS",
+    "workspace_bytes", "last_error", "version", "lib", "MalbecError", "STATUS", "adjoint",
+    "IntegrateFromParams",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -30,13 +31,13 @@ LIB_PATH = os.path.join(_HERE, "libmalbec.so")
 
 STATUS = {"ACTIVE": 0, "HORIZON": 1, "ESCAPE": 2, "DISK": 3, "NONFINITE": 4, "BUDGET": 5}
 F64, F32_KAHAN = 0, 1
-IC_CANONICAL, IC_CIRCULAR, IC_CONSTANTS = 0, 1, 2
-OP_INTEGRATE, OP_CAMERA = 1, 2
+IC_CANONICAL, IC_CIRCULAR, IC_CONSTANTS, IC_PARAMS = 0, 1, 2, 3
+OP_INTEGRATE, OP_CAMERA, OP_ADJOINT = 1, 2, 3
 MAX_SPACETIMES = 64
 
 # Algorithmic FP64 flops of one RK4 step of one lane as implemented (static count of
 # csrc/kerr_accel.hpp by csrc/flopcount.cpp: add/sub/mul/div 1, fma 2, sincos 2).
-FLOPS_PER_STEP_F64 = 582
+FLOPS_PER_STEP_F64 = 570
 
 
 class MalbecError(RuntimeError):
@@ -85,7 +86,7 @@ class c_camera(C.Structure):
 EXPORTS = {
     "malbec_last_error": (C.c_char_p, []),
     "malbec_version": (C.c_int, []),
-    "malbec_workspace_bytes": (C.c_size_t, [C.c_int32, C.c_int64]),
+    "malbec_workspace_bytes": (C.c_size_t, [C.c_int32, C.c_int64, C.c_int32]),
     "malbec_init_particles": (C.c_int, [C.POINTER(c_ic_spec), C.POINTER(c_batch), C.c_int64,
                                         C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "malbec_integrate": (C.c_int, [C.POINTER(c_run), C.POINTER(c_batch), C.c_int64, C.c_void_p,
@@ -95,6 +96,9 @@ EXPORTS = {
                                       C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "malbec_invariants": (C.c_int, [C.POINTER(c_batch), C.c_int64, C.c_void_p, C.c_void_p,
                                     C.c_void_p]),
+    "malbec_adjoint": (C.c_int, [C.POINTER(c_run), C.POINTER(c_batch), C.c_int64, C.c_void_p,
+                                 C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                 C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
 }
 
 _lib = None
@@ -123,8 +127,8 @@ def version() -> int:
     return lib().malbec_version()
 
 
-def workspace_bytes(op: int, n: int) -> int:
-    return lib().malbec_workspace_bytes(op, n)
+def workspace_bytes(op: int, n: int, aux: int = 0) -> int:
+    return lib().malbec_workspace_bytes(op, n, aux)
 
 
 def _check(rc):
@@ -194,7 +198,8 @@ class ICSpec:
                          (C.c_double * 2)(*self.r_range), (C.c_double * 2)(*self.th_range),
                          (C.c_double * 2)(*self.E_range), (C.c_double * 2)(*self.Lz_range),
                          (C.c_double * 2)(*self.Q_range), self.max_attempts,
-                         _ptr(self.rows, torch.float64, 8 * n if self.rows is not None else None,
+                         _ptr(self.rows, torch.float64,
+                              None if self.rows is None else (6 if self.mode == IC_PARAMS else 8) * n,
                               "rows"))
 
 
@@ -231,7 +236,7 @@ def integrate(state: torch.Tensor, status: torch.Tensor, steps: torch.Tensor, sp
         slots = n_steps // checkpoint_every + 1
         if checkpoints.numel() < slots * 8 * n:
             raise ValueError("checkpoints must hold %d slots of 8 x %d doubles" % (slots, n))
-    need = workspace_bytes(OP_INTEGRATE, n)
+    need = workspace_bytes(OP_INTEGRATE, n, 0)
     if need and ws is None:
         ws = torch.empty(need, dtype=torch.uint8, device=state.device)
     _check(lib().malbec_integrate(C.byref(run), C.byref(b.c), n,
@@ -292,7 +297,7 @@ def trace_camera(cam: Camera, final_state: bool = False, device="cuda", out=None
                "hit": torch.empty((2, npix), dtype=torch.float64, device=dev)}
         if final_state:
             out["final_state"] = torch.empty((8, npix), dtype=torch.float64, device=dev)
-    need = workspace_bytes(OP_CAMERA, npix)
+    need = workspace_bytes(OP_CAMERA, npix, 0)
     if ws is None:
         ws = torch.empty(need, dtype=torch.uint8, device=dev)
     cc = cam.to_c()
@@ -302,6 +307,67 @@ def trace_camera(cam: Camera, final_state: bool = False, device="cuda", out=None
                                      _ptr(out.get("final_state"), torch.float64, None),
                                      _ptr(ws), ws.numel(), _stream()))
     return out
+
+
+def adjoint(checkpoints: torch.Tensor, status: torch.Tensor, steps: torch.Tensor,
+            g_final: torch.Tensor, spacetimes, h: float, n_steps: int, checkpoint_every: int,
+            horizon_factor: float = 1.01, r_escape: float = 1500.0,
+            E_fixed: Optional[torch.Tensor] = None, named: bool = True, block: int = 0,
+            st_of_lane: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None):
+    """Discrete adjoint of a checkpointed FP64 integrate call.  Returns (g_initial[8, n],
+    g_named[5, n] or None)."""
+    n = g_final.shape[-1]
+    K = checkpoint_every
+    slots = n_steps // K + 1
+    if checkpoints.numel() < slots * 8 * n:
+        raise ValueError("checkpoints must hold %d slots of 8 x %d doubles" % (slots, n))
+    run = c_run(h, n_steps, F64, block, horizon_factor, r_escape, 1.0, 0, K)
+    b = _Batch(_spacetimes(spacetimes), st_of_lane, n)
+    g_initial = torch.empty((8, n), dtype=torch.float64, device=g_final.device)
+    g_named = torch.empty((5, n), dtype=torch.float64, device=g_final.device) if named else None
+    need = workspace_bytes(OP_ADJOINT, n, K)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=g_final.device)
+    _check(lib().malbec_adjoint(C.byref(run), C.byref(b.c), n, _ptr(checkpoints, torch.float64),
+                                _ptr(status, torch.int32, n, "status"),
+                                _ptr(steps, torch.int32, n, "steps"),
+                                _ptr(g_final, torch.float64, 8 * n, "g_final"),
+                                _ptr(g_initial), _ptr(E_fixed, torch.float64, n, "E_fixed"),
+                                _ptr(g_named), _ptr(ws), ws.numel(), _stream()))
+    return g_initial, g_named
+
+
+class IntegrateFromParams(torch.autograd.Function):
+    """y_N = RK4^N(y_0(p)), p = (r0, theta0, u^r0, u^theta0, L_z) [5, n] with E [n] held
+    fixed; backward runs the discrete adjoint (malbec_adjoint) from the checkpoints
+    saved by the forward pass.  Returns (y_N [8, n], status [n], steps [n])."""
+
+    @staticmethod
+    def forward(ctx, p, E, spacetime, h, n_steps, checkpoint_every, horizon_factor=1.01,
+                r_escape=1500.0):
+        n = p.shape[1]
+        rows = torch.cat([p.t(), E.reshape(n, 1)], dim=1).contiguous()
+        spec = ICSpec(mode=IC_PARAMS, rows=rows)
+        state, _, _ = init_particles(spec, [spacetime], n, device=p.device, want_consts=False,
+                                     want_attempts=False)
+        status, steps = new_lane_arrays(n, device=p.device)
+        K = checkpoint_every
+        ck = torch.empty((n_steps // K + 1, 8, n), dtype=torch.float64, device=p.device)
+        integrate(state, status, steps, [spacetime], h=h, n_steps=n_steps,
+                  horizon_factor=horizon_factor, r_escape=r_escape, checkpoints=ck,
+                  checkpoint_every=K)
+        ctx.save_for_backward(ck, status, steps, E)
+        ctx.cfg = (spacetime, h, n_steps, K, horizon_factor, r_escape)
+        ctx.mark_non_differentiable(status, steps)
+        return state, status, steps
+
+    @staticmethod
+    def backward(ctx, g_state, g_status, g_steps):
+        ck, status, steps, E = ctx.saved_tensors
+        spacetime, h, n_steps, K, hf, resc = ctx.cfg
+        _, g_named = adjoint(ck, status, steps, g_state.contiguous(), [spacetime], h, n_steps, K,
+                             horizon_factor=hf, r_escape=resc, E_fixed=E.contiguous())
+        return g_named, None, None, None, None, None, None, None
 
 
 def new_lane_arrays(n: int, device="cuda"):

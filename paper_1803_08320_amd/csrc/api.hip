@@ -55,10 +55,10 @@ const char *malbec_last_error(void) { return g_err; }
 
 int malbec_version(void) { return 10000 * 0 + 100 * 3 + 0; }
 
-size_t malbec_workspace_bytes(int32_t op, int64_t n)
+size_t malbec_workspace_bytes(int32_t op, int64_t n, int32_t aux)
 {
-    (void)n;
     if (op == MALBEC_OP_CAMERA) return 256;  // work counter (own cache line)
+    if (op == MALBEC_OP_ADJOINT && n > 0 && aux > 0) return (size_t)aux * 8 * (size_t)n * sizeof(double);
     return 0;
 }
 
@@ -79,6 +79,9 @@ int malbec_init_particles(const malbec_ic_spec *spec, const malbec_batch *b, int
     case MALBEC_IC_CIRCULAR:
         if (!(spec->r_lo > 0) || !(spec->r_hi >= spec->r_lo))
             return fail(MALBEC_EINVAL, "CIRCULAR: need 0 < r_lo <= r_hi");
+        break;
+    case MALBEC_IC_PARAMS:
+        if (n > 0 && !spec->rows) return fail(MALBEC_EINVAL, "PARAMS mode needs spec->rows");
         break;
     case MALBEC_IC_CONSTANTS:
         if (spec->max_attempts < 1 || spec->max_attempts >= (1 << 20))
@@ -124,7 +127,7 @@ int malbec_integrate(const malbec_run *run, const malbec_batch *b, int64_t n, do
     if (run->checkpoint_every < 0) return fail(MALBEC_EINVAL, "checkpoint_every < 0");
     if (run->checkpoint_every > 0 && !checkpoints)
         return fail(MALBEC_EINVAL, "checkpoint_every > 0 needs a checkpoints buffer");
-    size_t need = malbec_workspace_bytes(MALBEC_OP_INTEGRATE, n);
+    size_t need = malbec_workspace_bytes(MALBEC_OP_INTEGRATE, n, 0);
     if (ws_bytes < need || (need > 0 && !ws))
         return fail(MALBEC_ENOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, need);
     double zone = run->precision == MALBEC_F32_KAHAN ? run->fp64_zone_factor : 1.0;
@@ -173,7 +176,7 @@ int malbec_trace_camera(const malbec_camera *cam, int32_t *status, int32_t *step
     if (cam->block < 0 || cam->block > 1024 || (cam->block % 64) != 0)
         return fail(MALBEC_EINVAL, "block must be a multiple of 64 in [64, 1024] or 0");
     if (cam->steps_per_chunk < 0) return fail(MALBEC_EINVAL, "steps_per_chunk < 0");
-    size_t need = malbec_workspace_bytes(MALBEC_OP_CAMERA, npix);
+    size_t need = malbec_workspace_bytes(MALBEC_OP_CAMERA, npix, 0);
     if (ws_bytes < need || !ws)
         return fail(MALBEC_ENOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, need);
     double M = cam->M, a = cam->a;
@@ -188,6 +191,33 @@ int malbec_trace_camera(const malbec_camera *cam, int32_t *status, int32_t *step
     }
     return launch_camera(*cam, cam->horizon_factor * rp, r_in, status, steps, hit, final_state, ws,
                          (hipStream_t)stream);
+}
+
+int malbec_adjoint(const malbec_run *run, const malbec_batch *b, int64_t n,
+                   const double *checkpoints, const int32_t *status, const int32_t *steps,
+                   const double *g_final, double *g_initial, const double *E_fixed,
+                   double *g_named, void *ws, size_t ws_bytes, void *stream)
+{
+    clear_error();
+    if (!run) return fail(MALBEC_EINVAL, "run is NULL");
+    if (n < 0) return fail(MALBEC_EINVAL, "n < 0");
+    if (n > 0 && (!checkpoints || !status || !steps || !g_final || !g_initial))
+        return fail(MALBEC_EINVAL, "checkpoints, status, steps, g_final and g_initial must be non-NULL");
+    if (!(run->h > 0.0) || !isfinite(run->h)) return fail(MALBEC_EINVAL, "h must be > 0");
+    if (run->n_steps < 1 || run->n_steps > INT32_MAX) return fail(MALBEC_EINVAL, "n_steps outside [1, 2^31)");
+    if (run->checkpoint_every < 1) return fail(MALBEC_EINVAL, "checkpoint_every must be >= 1");
+    if (run->precision != MALBEC_F64) return fail(MALBEC_ENOTSUP, "the adjoint is FP64 only");
+    if (run->block < 0 || run->block > 1024 || (run->block % 64) != 0)
+        return fail(MALBEC_EINVAL, "block must be a multiple of 64 in [64, 1024] or 0");
+    size_t need = malbec_workspace_bytes(MALBEC_OP_ADJOINT, n, run->checkpoint_every);
+    if (ws_bytes < need || (need > 0 && !ws))
+        return fail(MALBEC_ENOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, need);
+    StTable T;
+    int rc = make_table(b, run->horizon_factor, 1.0, T);
+    if (rc) return rc;
+    if (n == 0) return MALBEC_OK;
+    return launch_adjoint(*run, T, b->st_of_lane, n, checkpoints, status, steps, g_final, g_initial,
+                          E_fixed, g_named, ws, (hipStream_t)stream);
 }
 
 int malbec_invariants(const malbec_batch *b, int64_t n, const double *state, double *out,

@@ -23,6 +23,9 @@ inline Counted operator/(Counted a, Counted b) { ++g_div; g_flops += 1; return C
 inline Counted operator-(Counted a) { return Counted(-a.v); }
 inline Counted &operator+=(Counted &a, Counted b) { a = a + b; return a; }
 inline Counted fma(Counted a, Counted b, Counted c) { ++g_fma; g_flops += 2; return Counted(a.v * b.v + c.v); }
+namespace malbec {
+inline Counted recip(Counted x) { ++g_div; g_flops += 1; return Counted(1.0 / x.v); }
+}
 
 #include <cmath>
 #include "kerr_accel.hpp"

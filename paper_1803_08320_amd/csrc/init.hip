@@ -9,6 +9,7 @@
 // Random numbers: SplitMix64 (Steele, Lea & Flood 2014) used as a counter-based
 // generator, draw k of attempt j of lane i = output (i*2^24 + j*2^4 + k + 1) of the
 // sequence started at `seed`.
+#include "ic_device.hpp"
 #include "internal.hpp"
 
 namespace malbec {
@@ -40,59 +41,6 @@ struct InitArgs {
     int64_t *attempts;
 };
 
-// Inverse-metric pieces at (r, theta): g^tt, g^tphi, g^phiphi, g^rr, g^thth.
-__device__ __forceinline__ void inverse_metric(double M, double a, double r, double s, double c,
-                                               double &itt, double &itp, double &ipp, double &irr,
-                                               double &ithth)
-{
-    const double a2 = a * a, s2 = s * s, r2 = r * r;
-    const double rho2 = r2 + a2 * c * c;
-    const double Delta = r2 - 2.0 * M * r + a2;
-    const double Sigma = (r2 + a2) * (r2 + a2) - a2 * Delta * s2;
-    const double den = rho2 * Delta;
-    itt = -Sigma / den;
-    itp = -2.0 * M * a * r / den;
-    ipp = (Delta - a2 * s2) / (den * s2);
-    irr = Delta / rho2;
-    ithth = 1.0 / rho2;
-}
-
-// 4-velocity from the constants of motion (Carter): with P = E (r^2 + a^2) - a L_z,
-// rho^2 u^r = s_r sqrt(R), rho^2 u^theta = s_th sqrt(Theta),
-// rho^2 u^t = (r^2 + a^2) P / Delta + a (L_z - a E sin^2),
-// rho^2 u^phi = a P / Delta + L_z / sin^2 - a E.
-__device__ __forceinline__ void velocity(double M, double a, double E, double Lz, double Q,
-                                         double mu2, double r, double s, double c, double sr,
-                                         double sth, double R, double Th, double u[4])
-{
-    const double a2 = a * a, s2 = s * s, r2 = r * r;
-    const double rho2 = r2 + a2 * c * c;
-    const double Delta = r2 - 2.0 * M * r + a2;
-    const double P = E * (r2 + a2) - a * Lz;
-    (void)mu2;
-    (void)Q;
-    u[0] = ((r2 + a2) * P / Delta + a * (Lz - a * E * s2)) / rho2;
-    u[1] = sr * sqrt(fmax(R, 0.0)) / rho2;
-    u[2] = sth * sqrt(fmax(Th, 0.0)) / rho2;
-    u[3] = (a * P / Delta + Lz / s2 - a * E) / rho2;
-}
-
-__device__ __forceinline__ double radial_potential(double M, double a, double E, double Lz, double Q,
-                                                   double mu2, double r)
-{
-    const double a2 = a * a, r2 = r * r;
-    const double P = E * (r2 + a2) - a * Lz;
-    const double Delta = r2 - 2.0 * M * r + a2;
-    const double L = Lz - a * E;
-    return P * P - Delta * (mu2 * r2 + L * L + Q);
-}
-
-__device__ __forceinline__ double polar_potential(double a, double E, double Lz, double Q, double mu2,
-                                                  double s, double c)
-{
-    return Q - c * c * (a * a * (mu2 - E * E) + Lz * Lz / (s * s));
-}
-
 __global__ void __launch_bounds__(256) init_kernel(InitArgs A, StTable T)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -122,6 +70,20 @@ __global__ void __launch_bounds__(256) init_kernel(InitArgs A, StTable T)
         y[7] = itp * pt + ipp * z[7];
         cE = z[4];
         cL = z[7];
+        cmu2 = 1.0;
+    } else if (P.mode == MALBEC_IC_PARAMS) {
+        const double *z = P.rows + 6 * i;  // r0, theta0, u^r0, u^theta0, L_z, E
+        double s, c;
+        sincos(z[1], &s, &c);
+        double itt, itp, ipp, irr, ithth;
+        inverse_metric(M, a, z[0], s, c, itt, itp, ipp, irr, ithth);
+        y[0] = 0.0; y[1] = z[0]; y[2] = z[1]; y[3] = 0.0;
+        y[4] = itt * (-z[5]) + itp * z[4];
+        y[5] = z[2];
+        y[6] = z[3];
+        y[7] = itp * (-z[5]) + ipp * z[4];
+        cE = z[5];
+        cL = z[4];
         cmu2 = 1.0;
     } else if (P.mode == MALBEC_IC_CIRCULAR) {
         const double rg[2] = {P.r_lo, P.r_hi};

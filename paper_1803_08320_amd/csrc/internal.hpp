@@ -52,6 +52,10 @@ int launch_integrate_f32k(const malbec_run &run, const StTable &T, const int32_t
                           hipStream_t s);
 int launch_camera(const malbec_camera &cam, double r_stop, double disk_r_in, int32_t *status,
                   int32_t *steps, double *hit, double *final_state, void *ws, hipStream_t s);
+int launch_adjoint(const malbec_run &run, const StTable &T, const int32_t *st_of_lane, int64_t n,
+                   const double *checkpoints, const int32_t *status, const int32_t *steps,
+                   const double *g_final, double *g_initial, const double *E_fixed,
+                   double *g_named, void *ws, hipStream_t s);
 int launch_invariants(const StTable &T, const int32_t *st_of_lane, int64_t n,
                       const double *state, double *out, hipStream_t s);
 

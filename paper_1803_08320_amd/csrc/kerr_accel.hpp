@@ -26,11 +26,29 @@ using std::fma;
 
 namespace malbec {
 
-// du^mu/dtau for the 4-velocity (ut, ur, uth, uph) at (r, theta) with s = sin theta,
-// c = cos theta.  T = double or float.
+// Reciprocal used by the acceleration: FP64 keeps the correctly rounded division;
+// FP32 on the device uses the hardware reciprocal (1 ulp).
+MALBEC_HD inline double recip(double x) { return 1.0 / x; }
+MALBEC_HD inline float recip(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rcpf(x);
+#else
+    return 1.0f / x;
+#endif
+}
+
+// Position-dependent coefficients of the acceleration at (r, theta): the metric
+// components that enter the raising, the partial derivatives of the metric, and
+// a few products, with s = sin theta, c = cos theta.
 template <typename T>
-MALBEC_HD inline void kerr_accel(T M, T a, T r, T s, T c, T ut, T ur, T uth, T uph,
-                                           T &at, T &ar, T &ath, T &aph)
+struct KerrCoef {
+    T r, gtt, gtp, gpp, iDs2, irho2, Dirho2, a2sc;
+    T dgtt_r, dgtt_th, dgtp_r, dgtp_th, dgpp_r, dgpp_th, dgrr_r, dgrr_th;
+};
+
+template <typename T>
+MALBEC_HD inline void kerr_coef(T M, T a, T r, T s, T c, KerrCoef<T> &K)
 {
     const T a2 = a * a;
     const T s2 = s * s;
@@ -38,38 +56,56 @@ MALBEC_HD inline void kerr_accel(T M, T a, T r, T s, T c, T ut, T ur, T uth, T u
     const T r2 = r * r;
     const T rho2 = fma(a2, c * c, r2);
     const T Delta = fma(r, r - T(2) * M, a2);
-    const T inv = T(1) / (rho2 * Delta * s2);
-    const T iDs2 = inv * rho2;        // 1 / (Delta s^2)
+    const T inv = recip(rho2 * Delta * s2);
+    const T iDs2 = inv * rho2;          // 1 / (Delta s^2)
     const T irho2 = inv * (Delta * s2); // 1 / rho^2
-    const T iDelta = iDs2 * s2;       // 1 / Delta
+    const T iDelta = iDs2 * s2;         // 1 / Delta
 
     const T q = T(2) * M * r * irho2;
-    const T gtt = q - T(1);
-    const T gtp = -a * q * s2;
     const T A = r2 + a2;
-    const T gpp = fma(a2 * q, s2, A) * s2;
+    const T gpp_over_s2 = fma(a2 * q, s2, A);
 
-    // partial derivatives of q
+    // partial derivatives of q and of q s^2
     const T dq_r = T(2) * M * irho2 * fma(T(-2) * r2, irho2, T(1));
     const T twosc = T(2) * sc;
     const T dq_th = q * a2 * twosc * irho2;
-    // d(q s^2)/dtheta
     const T dqs2_th = fma(dq_th, s2, q * twosc);
-
-    const T dgtt_r = dq_r, dgtt_th = dq_th;
-    const T dgtp_r = -a * s2 * dq_r;
-    const T dgtp_th = -a * dqs2_th;
-    const T dgpp_r = fma(a2 * s2, dq_r, T(2) * r) * s2;
-    const T dgpp_th = fma(a2 * dqs2_th, s2, fma(a2 * q, s2, A) * twosc);
     const T grr = rho2 * iDelta;
-    const T dgrr_r = iDelta * fma(-grr, T(2) * (r - M), T(2) * r);
-    const T dgrr_th = -a2 * twosc * iDelta;
 
+    K.r = r;
+    K.gtt = q - T(1);
+    K.gtp = -a * q * s2;
+    K.gpp = gpp_over_s2 * s2;
+    K.iDs2 = iDs2;
+    K.irho2 = irho2;
+    K.Dirho2 = Delta * irho2;
+    K.a2sc = a2 * sc;
+    K.dgtt_r = dq_r;
+    K.dgtt_th = dq_th;
+    K.dgtp_r = -a * s2 * dq_r;
+    K.dgtp_th = -a * dqs2_th;
+    K.dgpp_r = fma(a2 * s2, dq_r, T(2) * r) * s2;
+    K.dgpp_th = fma(a2 * dqs2_th, s2, gpp_over_s2 * twosc);
+    K.dgrr_r = iDelta * fma(-grr, T(2) * (r - M), T(2) * r);
+    K.dgrr_th = -a2 * twosc * iDelta;
+}
+
+// Intermediate products of the contraction (kept for the adjoint).
+template <typename T>
+struct KerrContr {
+    T Pt_r, Pt_th, Pp_r, Pp_th, Wt, Wp, Fr, Fth;
+};
+
+// du^mu/dtau from the coefficients and the 4-velocity (ut, ur, uth, uph).
+template <typename T>
+MALBEC_HD inline void kerr_contract(const KerrCoef<T> &K, T ut, T ur, T uth, T uph, T &at, T &ar,
+                                    T &ath, T &aph, KerrContr<T> *keep = nullptr)
+{
     // (d_l g_{t b}) u^b and (d_l g_{phi b}) u^b for l = r, theta
-    const T Pt_r = fma(dgtt_r, ut, dgtp_r * uph);
-    const T Pt_th = fma(dgtt_th, ut, dgtp_th * uph);
-    const T Pp_r = fma(dgtp_r, ut, dgpp_r * uph);
-    const T Pp_th = fma(dgtp_th, ut, dgpp_th * uph);
+    const T Pt_r = fma(K.dgtt_r, ut, K.dgtp_r * uph);
+    const T Pt_th = fma(K.dgtt_th, ut, K.dgtp_th * uph);
+    const T Pp_r = fma(K.dgtp_r, ut, K.dgpp_r * uph);
+    const T Pp_th = fma(K.dgtp_th, ut, K.dgpp_th * uph);
 
     // lowered acceleration components F_mu = g_{mu nu} du^nu/dtau
     const T Wt = fma(ur, Pt_r, uth * Pt_th);   // F_t = -Wt
@@ -78,28 +114,40 @@ MALBEC_HD inline void kerr_accel(T M, T a, T r, T s, T c, T ut, T ur, T uth, T u
     const T Qth = fma(ut, Pt_th, uph * Pp_th); // (t,phi) part of (d_th g_ab) u^a u^b
     const T urur = ur * ur, uthuth = uth * uth, uruth = ur * uth;
     // F_r = Qr/2 + r uth^2 - dgrr_r ur^2 / 2 - dgrr_th ur uth
-    const T Fr = fma(T(0.5), fma(-dgrr_r, urur, Qr), fma(r, uthuth, -dgrr_th * uruth));
+    const T Fr = fma(T(0.5), fma(-K.dgrr_r, urur, Qr), fma(K.r, uthuth, -K.dgrr_th * uruth));
     // F_th = Qth/2 + dgrr_th ur^2 / 2 + a^2 s c uth^2 - 2 r ur uth
-    const T Fth = fma(T(0.5), fma(dgrr_th, urur, Qth), fma(a2 * sc, uthuth, T(-2) * r * uruth));
+    const T Fth = fma(T(0.5), fma(K.dgrr_th, urur, Qth), fma(K.a2sc, uthuth, T(-2) * K.r * uruth));
 
     // raise: (t, phi) block inverse = (1 / (-Delta s^2)) [[g_pp, -g_tp], [-g_tp, g_tt]]
-    at = iDs2 * fma(gpp, Wt, -gtp * Wp);
-    aph = iDs2 * fma(gtt, Wp, -gtp * Wt);
-    ar = Fr * Delta * irho2;
-    ath = Fth * irho2;
+    at = K.iDs2 * fma(K.gpp, Wt, -K.gtp * Wp);
+    aph = K.iDs2 * fma(K.gtt, Wp, -K.gtp * Wt);
+    ar = Fr * K.Dirho2;
+    ath = Fth * K.irho2;
+    if (keep) *keep = KerrContr<T>{Pt_r, Pt_th, Pp_r, Pp_th, Wt, Wp, Fr, Fth};
 }
 
-// One classic RK4 step (b = 1/6, 1/3, 1/3, 1/6; c = 0, 1/2, 1/2, 1) of all 8
-// components; accel(r, th, ut, ur, uth, uph, at, ar, ath, aph) evaluates du/dtau.  The right-hand side does not depend on t or phi, so only
-// (r, theta, u) are formed at the stage points; t and phi accumulate the stage
-// values of u^t and u^phi with the same weights.  sr[] receives the radii of the
-// three intermediate stage points.
+// du^mu/dtau for the 4-velocity (ut, ur, uth, uph) at (r, theta) with s = sin theta,
+// c = cos theta.  T = double or float.
+template <typename T>
+MALBEC_HD inline void kerr_accel(T M, T a, T r, T s, T c, T ut, T ur, T uth, T uph, T &at, T &ar,
+                                 T &ath, T &aph)
+{
+    KerrCoef<T> K;
+    kerr_coef(M, a, r, s, c, K);
+    kerr_contract(K, ut, ur, uth, uph, at, ar, ath, aph);
+}
+
+// Stages of one classic RK4 step (b = 1/6, 1/3, 1/3, 1/6; c = 0, 1/2, 1/2, 1) of all
+// 8 components; accel(r, th, ut, ur, uth, uph, at, ar, ath, aph) evaluates du/dtau.
+// The right-hand side does not depend on t or phi, so only (r, theta, u) are formed
+// at the stage points; t and phi accumulate the stage values of u^t and u^phi with
+// the same weights.  sr[] receives the radii of the three intermediate stage points
+// and acc[] the weighted sum k1 + 2 k2 + 2 k3 + k4.
 template <typename T, typename Accel>
-MALBEC_HD inline void rk4_step(const Accel &accel, T h, const T y[8], T y1[8], T sr[3])
+MALBEC_HD inline void rk4_stages(const Accel &accel, T h, const T y[8], T acc[8], T sr[3])
 {
     const T hh = T(0.5) * h;
     T at, ar, ath, aph;
-    T acc[8];
     T s1, s2, s3, s4, s5, s6; // stage point (r, th, ut, ur, uth, uph)
 
     // k1 = f(y)
@@ -140,11 +188,29 @@ MALBEC_HD inline void rk4_step(const Accel &accel, T h, const T y[8], T y1[8], T
     accel(s1, s2, s3, s4, s5, s6, at, ar, ath, aph);
     acc[0] += s3; acc[1] += s4; acc[2] += s5; acc[3] += s6;
     acc[4] += at; acc[5] += ar; acc[6] += ath; acc[7] += aph;
+}
 
+// y1 = y + h/6 (k1 + 2 k2 + 2 k3 + k4)
+template <typename T, typename Accel>
+MALBEC_HD inline void rk4_step(const Accel &accel, T h, const T y[8], T y1[8], T sr[3])
+{
+    T acc[8];
+    rk4_stages(accel, h, y, acc, sr);
     const T h6 = h * T(1.0 / 6.0);
     // acc[0..3] hold the weighted sums of (u^t, u^r, u^theta, u^phi) = dx/dtau
 #pragma unroll
     for (int k = 0; k < 8; ++k) y1[k] = fma(h6, acc[k], y[k]);
+}
+
+// The increment d = h/6 (k1 + 2 k2 + 2 k3 + k4) alone (compensated updates).
+template <typename T, typename Accel>
+MALBEC_HD inline void rk4_delta(const Accel &accel, T h, const T y[8], T d[8], T sr[3])
+{
+    T acc[8];
+    rk4_stages(accel, h, y, acc, sr);
+    const T h6 = h * T(1.0 / 6.0);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) d[k] = h6 * acc[k];
 }
 
 }  // namespace malbec

@@ -30,7 +30,7 @@ def declared_functions():
 
 def test_every_declared_symbol_is_exported(m):
     names = declared_functions()
-    assert len(names) >= 7
+    assert len(names) >= 8
     out = subprocess.run(["nm", "-D", "--defined-only", m.LIB_PATH], capture_output=True,
                          text=True, check=True).stdout
     exported = set(re.findall(r"\bT (malbec_\w+)", out))
@@ -139,6 +139,7 @@ def test_init_and_camera_argument_errors(m):
     assert m.lib().malbec_init_particles(C.byref(spec), C.byref(b), 4, FAKE, None, None, None) == -1
     cam = m.Camera(nx=4, ny=4).to_c()
     ws_need = m.workspace_bytes(m.OP_CAMERA, 16)
+    assert m.workspace_bytes(m.OP_ADJOINT, 100, 256) == 256 * 8 * 100 * 8
     assert ws_need >= 8
     # workspace too small
     assert m.lib().malbec_trace_camera(C.byref(cam), FAKE, FAKE, FAKE, None, FAKE, 4, None) == -2
@@ -150,6 +151,16 @@ def test_init_and_camera_argument_errors(m):
         assert m.lib().malbec_trace_camera(C.byref(cam), FAKE, FAKE, FAKE, None, FAKE, ws_need,
                                            None) == -1, bad
     assert m.lib().malbec_invariants(C.byref(b), -1, FAKE, FAKE, None) == -1
+    # adjoint: no checkpoint interval, no workspace, wrong precision
+    run = _run(m, checkpoint_every=0)
+    assert m.lib().malbec_adjoint(C.byref(run), C.byref(b), 4, FAKE, FAKE, FAKE, FAKE, FAKE, None,
+                                  None, FAKE, 10 ** 9, None) == -1
+    run = _run(m, checkpoint_every=4)
+    assert m.lib().malbec_adjoint(C.byref(run), C.byref(b), 4, FAKE, FAKE, FAKE, FAKE, FAKE, None,
+                                  None, FAKE, 8, None) == -2
+    run = _run(m, checkpoint_every=4, precision=1)
+    assert m.lib().malbec_adjoint(C.byref(run), C.byref(b), 4, FAKE, FAKE, FAKE, FAKE, FAKE, None,
+                                  None, FAKE, 10 ** 9, None) == -4
     assert m.version() >= 300
 
 
