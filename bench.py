@@ -41,6 +41,10 @@ def parse():
     p.add_argument("--cpu-lanes", type=int, default=1024,
                    help="oracle sample: this many strided lanes x the full step count")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-f32k", action="store_true", help="skip the FP32-compensated leg")
+    p.add_argument("--probe-copy-bytes", type=int, default=0,
+                   help="first run one device-to-device copy of this many bytes (a plain copy "
+                        "kernel of known size, used to calibrate HBM byte counters)")
     return p.parse_args()
 
 
@@ -61,6 +65,12 @@ def main():
     import paper_1803_08320_amd as m
 
     torch.cuda.set_device(0)
+    if args.probe_copy_bytes:
+        src = torch.ones(args.probe_copy_bytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     st = [(1.0, 0.9)]
     n, n_rk, h = args.lanes, args.rk_steps, 0.02
     spec = m.ICSpec(mode=m.IC_CONSTANTS, seed=2)
@@ -138,6 +148,48 @@ def main():
         "context": {"paper_gpu_lane_steps_per_s": 3.69e6,
                     "paper_hardware": "GTX 960M, Kerr a=0.5, h=0.1, FP64, no I/O"},
     }
+
+    if not args.no_f32k:
+        # FP32 state with compensated update, FP64 within 1.2 r_+: same ICs, one timed run
+        fin64 = state.clone()
+        st64 = status.clone()
+        state.copy_(s0)
+        status.zero_()
+        steps.zero_()
+        m.integrate(state, status, steps, st, h=h, n_steps=n_rk, precision="f32k",
+                    fp64_zone_factor=1.2, block=args.block)  # warm-up
+        state.copy_(s0)
+        status.zero_()
+        steps.zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        m.integrate(state, status, steps, st, h=h, n_steps=n_rk, precision="f32k",
+                    fp64_zone_factor=1.2, block=args.block)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        k_steps = int(steps.sum().item())
+        m.invariants(state, st, out=inv1)
+        j1 = inv1.cpu().numpy()
+        act32 = (status == 0).cpu().numpy() & act
+        dE32 = np.abs(j1[0] / i0[0] - 1)[act32]
+        q32 = act32 & (i0[2] >= 0.1)
+        dQ32 = np.abs(j1[2] / i0[2] - 1)[q32]
+        a64, a32 = fin64.cpu().numpy(), state.cpu().numpy()
+
+        def cart(y):
+            rr = np.sqrt(y[1] ** 2 + 0.81)
+            return np.stack([rr * np.sin(y[2]) * np.cos(y[3]), rr * np.sin(y[2]) * np.sin(y[3]),
+                             y[1] * np.cos(y[2])])
+        pos = (np.linalg.norm(cart(a32) - cart(a64), axis=0) / a64[1])[act32]
+        v32 = k_steps / dt
+        result["f32k"] = {"value": v32, "unit": "lane-steps/s", "speedup_vs_f64": v32 / result["value"],
+                          "zone": "FP64 steps inside 1.2 r_+",
+                          "dE_over_E_p99": float(np.quantile(dE32, 0.99)),
+                          "dQ_over_Q_p99": float(np.quantile(dQ32, 0.99)),
+                          "dQ_over_Q_max": float(dQ32.max()),
+                          "pos_err_vs_f64_p50": float(np.quantile(pos, 0.5)),
+                          "pos_err_vs_f64_p99": float(np.quantile(pos, 0.99)),
+                          "status_agree_frac": float(((status == st64).float().mean()).item())}
 
     if not args.no_cpu_baseline:
         import oracle

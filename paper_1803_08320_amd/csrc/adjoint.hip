@@ -140,17 +140,17 @@ __device__ __forceinline__ void jt(const Spacetime &S, const double Y[6], const 
 // rk4_stages).
 __device__ __forceinline__ void vjp_step(const Spacetime &S, double h, const double y[8], double lam[8])
 {
-    const AccelF64 f{S.M, S.a};
+    AccelF64 f{S.M, S.a, 0.0, 0.0, 1.0};
     const double hh = 0.5 * h;
     double Y1[6] = {y[1], y[2], y[4], y[5], y[6], y[7]};
     double at, ar, ath, aph;
-    f(Y1[0], Y1[1], Y1[2], Y1[3], Y1[4], Y1[5], at, ar, ath, aph);
+    f(0, Y1[0], Y1[1], Y1[2], Y1[3], Y1[4], Y1[5], at, ar, ath, aph);
     double Y2[6] = {fma(hh, y[5], y[1]), fma(hh, y[6], y[2]), fma(hh, at, y[4]), fma(hh, ar, y[5]),
                     fma(hh, ath, y[6]), fma(hh, aph, y[7])};
-    f(Y2[0], Y2[1], Y2[2], Y2[3], Y2[4], Y2[5], at, ar, ath, aph);
+    f(1, Y2[0], Y2[1], Y2[2], Y2[3], Y2[4], Y2[5], at, ar, ath, aph);
     double Y3[6] = {fma(hh, Y2[3], y[1]), fma(hh, Y2[4], y[2]), fma(hh, at, y[4]), fma(hh, ar, y[5]),
                     fma(hh, ath, y[6]), fma(hh, aph, y[7])};
-    f(Y3[0], Y3[1], Y3[2], Y3[3], Y3[4], Y3[5], at, ar, ath, aph);
+    f(2, Y3[0], Y3[1], Y3[2], Y3[3], Y3[4], Y3[5], at, ar, ath, aph);
     double Y4[6] = {fma(h, Y3[3], y[1]), fma(h, Y3[4], y[2]), fma(h, at, y[4]), fma(h, ar, y[5]),
                     fma(h, ath, y[6]), fma(h, aph, y[7])};
 

@@ -4,7 +4,8 @@
 // counting scalar type.  Counting rule: add, sub, mul, div = 1 flop each,
 // fma = 2 flops, sincos = 2 (two results), negation = 0.  The count is
 // independent of the data (the code is straight-line), so one evaluation gives
-// the algorithmic flops per lane-step used for the roofline.
+// the algorithmic flops per lane-step used for the roofline.  sin/cos of a stage
+// angle count 2 however the kernel obtains them (library sincos or rotation).
 //   g++ -O0 -std=c++17 flopcount.cpp -o flopcount && ./flopcount
 #include <cstdio>
 
@@ -32,7 +33,7 @@ inline Counted recip(Counted x) { ++g_div; g_flops += 1; return Counted(1.0 / x.
 
 struct AccelCount {
     Counted M, a;
-    void operator()(Counted r, Counted th, Counted ut, Counted ur, Counted uth, Counted uph,
+    void operator()(int, Counted r, Counted th, Counted ut, Counted ur, Counted uth, Counted uph,
                     Counted &at, Counted &ar, Counted &ath, Counted &aph) const
     {
         g_flops += 2;  // sincos
@@ -47,7 +48,7 @@ int main()
     AccelCount f{Counted(1.0), Counted(0.9)};
     Counted at, ar, ath, aph;
     g_flops = g_div = g_fma = g_addmul = 0;
-    f(y[1], y[2], y[4], y[5], y[6], y[7], at, ar, ath, aph);
+    f(0, y[1], y[2], y[4], y[5], y[6], y[7], at, ar, ath, aph);
     long rhs = g_flops, rhs_div = g_div, rhs_fma = g_fma, rhs_am = g_addmul;
     g_flops = g_div = g_fma = g_addmul = 0;
     malbec::rk4_step(f, Counted(0.02), y, y1, sr);

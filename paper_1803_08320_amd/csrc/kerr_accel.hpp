@@ -26,9 +26,20 @@ using std::fma;
 
 namespace malbec {
 
-// Reciprocal used by the acceleration: FP64 keeps the correctly rounded division;
-// FP32 on the device uses the hardware reciprocal (1 ulp).
-MALBEC_HD inline double recip(double x) { return 1.0 / x; }
+// Reciprocal used by the acceleration.  On the device: FP64 from the hardware
+// estimate refined by two Newton steps, FP32 the hardware reciprocal (1 ulp).
+MALBEC_HD inline double recip(double x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+#else
+    return 1.0 / x;
+#endif
+}
 MALBEC_HD inline float recip(float x)
 {
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -138,20 +149,21 @@ MALBEC_HD inline void kerr_accel(T M, T a, T r, T s, T c, T ut, T ur, T uth, T u
 }
 
 // Stages of one classic RK4 step (b = 1/6, 1/3, 1/3, 1/6; c = 0, 1/2, 1/2, 1) of all
-// 8 components; accel(r, th, ut, ur, uth, uph, at, ar, ath, aph) evaluates du/dtau.
+// 8 components; accel(stage, r, th, ut, ur, uth, uph, at, ar, ath, aph) evaluates
+// du/dtau at stage point `stage` (0 = the step's start).
 // The right-hand side does not depend on t or phi, so only (r, theta, u) are formed
 // at the stage points; t and phi accumulate the stage values of u^t and u^phi with
 // the same weights.  sr[] receives the radii of the three intermediate stage points
 // and acc[] the weighted sum k1 + 2 k2 + 2 k3 + k4.
 template <typename T, typename Accel>
-MALBEC_HD inline void rk4_stages(const Accel &accel, T h, const T y[8], T acc[8], T sr[3])
+MALBEC_HD inline void rk4_stages(Accel &accel, T h, const T y[8], T acc[8], T sr[3])
 {
     const T hh = T(0.5) * h;
     T at, ar, ath, aph;
     T s1, s2, s3, s4, s5, s6; // stage point (r, th, ut, ur, uth, uph)
 
     // k1 = f(y)
-    accel(y[1], y[2], y[4], y[5], y[6], y[7], at, ar, ath, aph);
+    accel(0, y[1], y[2], y[4], y[5], y[6], y[7], at, ar, ath, aph);
     acc[0] = y[4]; acc[1] = y[5]; acc[2] = y[6]; acc[3] = y[7];
     acc[4] = at; acc[5] = ar; acc[6] = ath; acc[7] = aph;
     s1 = fma(hh, y[5], y[1]); s2 = fma(hh, y[6], y[2]);
@@ -159,7 +171,7 @@ MALBEC_HD inline void rk4_stages(const Accel &accel, T h, const T y[8], T acc[8]
     sr[0] = s1;
 
     // k2 = f(y + h/2 k1)
-    accel(s1, s2, s3, s4, s5, s6, at, ar, ath, aph);
+    accel(1, s1, s2, s3, s4, s5, s6, at, ar, ath, aph);
     acc[0] = fma(T(2), s3, acc[0]); acc[1] = fma(T(2), s4, acc[1]);
     acc[2] = fma(T(2), s5, acc[2]); acc[3] = fma(T(2), s6, acc[3]);
     acc[4] = fma(T(2), at, acc[4]); acc[5] = fma(T(2), ar, acc[5]);
@@ -172,7 +184,7 @@ MALBEC_HD inline void rk4_stages(const Accel &accel, T h, const T y[8], T acc[8]
     sr[1] = s1;
 
     // k3 = f(y + h/2 k2)
-    accel(s1, s2, s3, s4, s5, s6, at, ar, ath, aph);
+    accel(2, s1, s2, s3, s4, s5, s6, at, ar, ath, aph);
     acc[0] = fma(T(2), s3, acc[0]); acc[1] = fma(T(2), s4, acc[1]);
     acc[2] = fma(T(2), s5, acc[2]); acc[3] = fma(T(2), s6, acc[3]);
     acc[4] = fma(T(2), at, acc[4]); acc[5] = fma(T(2), ar, acc[5]);
@@ -185,14 +197,14 @@ MALBEC_HD inline void rk4_stages(const Accel &accel, T h, const T y[8], T acc[8]
     sr[2] = s1;
 
     // k4 = f(y + h k3)
-    accel(s1, s2, s3, s4, s5, s6, at, ar, ath, aph);
+    accel(3, s1, s2, s3, s4, s5, s6, at, ar, ath, aph);
     acc[0] += s3; acc[1] += s4; acc[2] += s5; acc[3] += s6;
     acc[4] += at; acc[5] += ar; acc[6] += ath; acc[7] += aph;
 }
 
 // y1 = y + h/6 (k1 + 2 k2 + 2 k3 + k4)
 template <typename T, typename Accel>
-MALBEC_HD inline void rk4_step(const Accel &accel, T h, const T y[8], T y1[8], T sr[3])
+MALBEC_HD inline void rk4_step(Accel &accel, T h, const T y[8], T y1[8], T sr[3])
 {
     T acc[8];
     rk4_stages(accel, h, y, acc, sr);
@@ -204,7 +216,7 @@ MALBEC_HD inline void rk4_step(const Accel &accel, T h, const T y[8], T y1[8], T
 
 // The increment d = h/6 (k1 + 2 k2 + 2 k3 + k4) alone (compensated updates).
 template <typename T, typename Accel>
-MALBEC_HD inline void rk4_delta(const Accel &accel, T h, const T y[8], T d[8], T sr[3])
+MALBEC_HD inline void rk4_delta(Accel &accel, T h, const T y[8], T d[8], T sr[3])
 {
     T acc[8];
     rk4_stages(accel, h, y, acc, sr);

@@ -16,9 +16,9 @@ namespace {
 
 struct AccelF32 {
     float M, a;
-    __device__ __forceinline__ void operator()(float r, float th, float ut, float ur, float uth,
-                                               float uph, float &at, float &ar, float &ath,
-                                               float &aph) const
+    __device__ __forceinline__ void operator()(int, float r, float th, float ut, float ur,
+                                               float uth, float uph, float &at, float &ar,
+                                               float &ath, float &aph) const
     {
         float s, c;
         sincosf(th, &s, &c);
@@ -76,7 +76,7 @@ __global__ void __launch_bounds__(256) rk4_f32k_kernel(MixArgs A, StTable T)
     }
     if (st != kActive) return;
     const Spacetime S = MULTI ? lds_st[sid] : T.st[0];
-    const AccelF32 f32{(float)S.M, (float)S.a};
+    AccelF32 f32{(float)S.M, (float)S.a};
     const float h32 = (float)A.h;
 
     float hi[8], lo[8];
