@@ -128,8 +128,13 @@ typedef struct {
     double horizon_factor;   /* stop at r <= horizon_factor * r_+ ; >= 1 (1.01 typical) */
     double r_escape;         /* stop at r >= r_escape */
     double fp64_zone_factor; /* F32_KAHAN: steps starting at r < factor * r_+ run in FP64 */
-    int32_t steps_per_chunk; /* steps per kernel launch, 0 = all n_steps in one launch */
+    int32_t steps_per_chunk; /* persistent = 0: steps per kernel launch (0 = all n_steps in
+                                one launch); persistent = 1: steps between retire/refill
+                                checks (0 = 64) */
     int32_t checkpoint_every;/* K > 0: write the state every K steps (see malbec_integrate) */
+    int32_t persistent;      /* 1: persistent kernel refilling lanes that stop early from a
+                                work counter in ws (needs persistent = 0 for checkpoints) */
+    int32_t pad_;
 } malbec_run;
 
 /* Camera (malbec_trace_camera): Bardeen image plane of a static observer at
@@ -160,9 +165,10 @@ MALBEC_API const char *malbec_last_error(void);
 /* Library version as 10000 * major + 100 * minor + patch. */
 MALBEC_API int malbec_version(void);
 
-/* Bytes of caller workspace an operation needs: op = MALBEC_OP_INTEGRATE (n lanes),
- * MALBEC_OP_CAMERA (n = nx * ny pixels) or MALBEC_OP_ADJOINT (n lanes, aux = the
- * checkpoint interval K: K * 8 * n doubles).  Returns 0 for operations that need none. */
+/* Bytes of caller workspace an operation needs: op = MALBEC_OP_INTEGRATE (n lanes,
+ * aux = run->persistent), MALBEC_OP_CAMERA (n = nx * ny pixels) or MALBEC_OP_ADJOINT
+ * (n lanes, aux = the checkpoint interval K: K * 8 * n doubles).  Returns 0 for
+ * operations that need none. */
 MALBEC_API size_t malbec_workspace_bytes(int32_t op, int64_t n, int32_t aux);
 
 /* Build the initial state of n lanes on the device (one GPU thread per lane).
@@ -187,7 +193,8 @@ MALBEC_API int malbec_init_particles(const malbec_ic_spec *spec, const malbec_ba
  * checkpoints: device (nullable, F64 only): if run->checkpoint_every = K > 0, slot
  * s = 0 .. n_steps/K receives the state after s*K steps of this call, at
  * checkpoints[s * 8n + k * n + i]; a lane stopped earlier repeats its final state.
- * ws / ws_bytes: caller workspace (malbec_workspace_bytes(MALBEC_OP_INTEGRATE, n)).
+ * ws / ws_bytes: caller workspace of malbec_workspace_bytes(MALBEC_OP_INTEGRATE, n,
+ * run->persistent) bytes (the persistent kernel's work counter; 0 bytes otherwise).
  * Errors: MALBEC_EINVAL, MALBEC_ENOMEM, MALBEC_EDEVICE. */
 MALBEC_API int malbec_integrate(const malbec_run *run, const malbec_batch *b, int64_t n, double *state,
                      int32_t *status, int32_t *steps, double *checkpoints, void *ws,

@@ -70,7 +70,7 @@ class c_run(C.Structure):
     _fields_ = [("h", C.c_double), ("n_steps", C.c_int64), ("precision", C.c_int32),
                 ("block", C.c_int32), ("horizon_factor", C.c_double), ("r_escape", C.c_double),
                 ("fp64_zone_factor", C.c_double), ("steps_per_chunk", C.c_int32),
-                ("checkpoint_every", C.c_int32)]
+                ("checkpoint_every", C.c_int32), ("persistent", C.c_int32), ("pad_", C.c_int32)]
 
 
 class c_camera(C.Structure):
@@ -223,12 +223,12 @@ def integrate(state: torch.Tensor, status: torch.Tensor, steps: torch.Tensor, sp
               precision: str = "f64", fp64_zone_factor: float = 1.2, block: int = 0,
               steps_per_chunk: int = 0, st_of_lane: Optional[torch.Tensor] = None,
               checkpoints: Optional[torch.Tensor] = None, checkpoint_every: int = 0,
-              ws: Optional[torch.Tensor] = None):
+              persistent: bool = False, ws: Optional[torch.Tensor] = None):
     """Advance state[8, n] in place (status, steps int32[n] in/out)."""
     n = state.shape[-1]
     prec = {"f64": F64, "f32k": F32_KAHAN}[precision]
     run = c_run(h, n_steps, prec, block, horizon_factor, r_escape, fp64_zone_factor,
-                steps_per_chunk, checkpoint_every)
+                steps_per_chunk, checkpoint_every, int(persistent), 0)
     b = _Batch(_spacetimes(spacetimes), st_of_lane, n)
     if checkpoint_every > 0:
         if checkpoints is None:
@@ -236,7 +236,7 @@ def integrate(state: torch.Tensor, status: torch.Tensor, steps: torch.Tensor, sp
         slots = n_steps // checkpoint_every + 1
         if checkpoints.numel() < slots * 8 * n:
             raise ValueError("checkpoints must hold %d slots of 8 x %d doubles" % (slots, n))
-    need = workspace_bytes(OP_INTEGRATE, n, 0)
+    need = workspace_bytes(OP_INTEGRATE, n, int(persistent))
     if need and ws is None:
         ws = torch.empty(need, dtype=torch.uint8, device=state.device)
     _check(lib().malbec_integrate(C.byref(run), C.byref(b.c), n,
@@ -321,7 +321,7 @@ def adjoint(checkpoints: torch.Tensor, status: torch.Tensor, steps: torch.Tensor
     slots = n_steps // K + 1
     if checkpoints.numel() < slots * 8 * n:
         raise ValueError("checkpoints must hold %d slots of 8 x %d doubles" % (slots, n))
-    run = c_run(h, n_steps, F64, block, horizon_factor, r_escape, 1.0, 0, K)
+    run = c_run(h, n_steps, F64, block, horizon_factor, r_escape, 1.0, 0, K, 0, 0)
     b = _Batch(_spacetimes(spacetimes), st_of_lane, n)
     g_initial = torch.empty((8, n), dtype=torch.float64, device=g_final.device)
     g_named = torch.empty((5, n), dtype=torch.float64, device=g_final.device) if named else None

@@ -22,6 +22,23 @@ int fail(int code, const char *fmt, ...)
 
 void clear_error() { g_err[0] = '\0'; }
 
+int persistent_grid(const void *kernel, int block, int64_t n_items, int &grid)
+{
+    int dev = 0;
+    MALBEC_HIP_CHECK(hipGetDevice(&dev));
+    int n_cu = 0;
+    MALBEC_HIP_CHECK(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    int per_cu = 0;
+    MALBEC_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0));
+    if (per_cu < 1) per_cu = 1;
+    int64_t g = (int64_t)n_cu * per_cu;
+    const int64_t need = (n_items + block - 1) / block;
+    if (g > need) g = need;
+    if (g < 1) g = 1;
+    grid = (int)g;
+    return MALBEC_OK;
+}
+
 int make_table(const malbec_batch *b, double horizon_factor, double zone_factor, StTable &T)
 {
     if (!b || !b->st) return fail(MALBEC_EINVAL, "batch or batch->st is NULL");
@@ -58,6 +75,7 @@ int malbec_version(void) { return 10000 * 0 + 100 * 3 + 0; }
 size_t malbec_workspace_bytes(int32_t op, int64_t n, int32_t aux)
 {
     if (op == MALBEC_OP_CAMERA) return 256;  // work counter (own cache line)
+    if (op == MALBEC_OP_INTEGRATE && aux) return 256;  // persistent kernel's work counter
     if (op == MALBEC_OP_ADJOINT && n > 0 && aux > 0) return (size_t)aux * 8 * (size_t)n * sizeof(double);
     return 0;
 }
@@ -111,7 +129,6 @@ int malbec_integrate(const malbec_run *run, const malbec_batch *b, int64_t n, do
                      size_t ws_bytes, void *stream)
 {
     clear_error();
-    (void)ws;
     if (!run) return fail(MALBEC_EINVAL, "run is NULL");
     if (n < 0) return fail(MALBEC_EINVAL, "n = %lld < 0", (long long)n);
     if (n > 0 && (!state || !status || !steps))
@@ -127,7 +144,10 @@ int malbec_integrate(const malbec_run *run, const malbec_batch *b, int64_t n, do
     if (run->checkpoint_every < 0) return fail(MALBEC_EINVAL, "checkpoint_every < 0");
     if (run->checkpoint_every > 0 && !checkpoints)
         return fail(MALBEC_EINVAL, "checkpoint_every > 0 needs a checkpoints buffer");
-    size_t need = malbec_workspace_bytes(MALBEC_OP_INTEGRATE, n, 0);
+    if (run->persistent != 0 && run->persistent != 1) return fail(MALBEC_EINVAL, "persistent must be 0 or 1");
+    if (run->persistent && run->checkpoint_every > 0)
+        return fail(MALBEC_ENOTSUP, "checkpoints need persistent = 0");
+    size_t need = malbec_workspace_bytes(MALBEC_OP_INTEGRATE, n, run->persistent);
     if (ws_bytes < need || (need > 0 && !ws))
         return fail(MALBEC_ENOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, need);
     double zone = run->precision == MALBEC_F32_KAHAN ? run->fp64_zone_factor : 1.0;
@@ -141,13 +161,13 @@ int malbec_integrate(const malbec_run *run, const malbec_batch *b, int64_t n, do
     }
     if (run->precision == MALBEC_F64)
         return launch_integrate_f64(*run, T, b->st_of_lane, n, state, status, steps, checkpoints,
-                                    (hipStream_t)stream);
+                                    ws, (hipStream_t)stream);
     if (run->precision == MALBEC_F32_KAHAN) {
         if (run->checkpoint_every > 0)
             return fail(MALBEC_ENOTSUP, "checkpoints are FP64 only");
         if (!(run->fp64_zone_factor >= 1.0))
             return fail(MALBEC_EINVAL, "fp64_zone_factor = %g must be >= 1", run->fp64_zone_factor);
-        return launch_integrate_f32k(*run, T, b->st_of_lane, n, state, status, steps,
+        return launch_integrate_f32k(*run, T, b->st_of_lane, n, state, status, steps, ws,
                                      (hipStream_t)stream);
     }
     return fail(MALBEC_EINVAL, "unknown precision %d", run->precision);

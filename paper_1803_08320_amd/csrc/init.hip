@@ -27,9 +27,22 @@ __device__ __forceinline__ uint64_t splitmix_out(uint64_t seed, uint64_t lane, u
 
 __device__ __forceinline__ double unit53(uint64_t x) { return (double)(x >> 11) * 0x1.0p-53; }
 
+// lo + (hi - lo) u, rounded after each operation (no fused multiply-add), so that
+// the drawn values are the same bits on every implementation of the recipe.
 __device__ __forceinline__ double uniform(const double rg[2], uint64_t x)
 {
-    return rg[0] + (rg[1] - rg[0]) * unit53(x);
+#pragma clang fp contract(off)
+    const double span = rg[1] - rg[0];
+    const double scaled = span * unit53(x);
+    return rg[0] + scaled;
+}
+
+// dL (2u - 1) with separately rounded operations.
+__device__ __forceinline__ double centred(double dL, uint64_t x)
+{
+#pragma clang fp contract(off)
+    const double twice = 2.0 * unit53(x);
+    return dL * (twice - 1.0);
 }
 
 struct InitArgs {
@@ -88,7 +101,7 @@ __global__ void __launch_bounds__(256) init_kernel(InitArgs A, StTable T)
     } else if (P.mode == MALBEC_IC_CIRCULAR) {
         const double rg[2] = {P.r_lo, P.r_hi};
         const double r0 = uniform(rg, splitmix_out(P.seed, lane, 0, 0));
-        const double delta = P.dL * (2.0 * unit53(splitmix_out(P.seed, lane, 0, 1)) - 1.0);
+        const double delta = centred(P.dL, splitmix_out(P.seed, lane, 0, 1));
         // Bardeen-Press-Teukolsky circular orbit, upper sign prograde
         const double sg = P.prograde ? 1.0 : -1.0;
         const double sr = sqrt(r0), sM = sqrt(M);

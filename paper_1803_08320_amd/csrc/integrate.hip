@@ -6,6 +6,7 @@
 // launch; the work is FP64 VALU arithmetic.  Spacetime constants come from the
 // kernel arguments (uniform batch) or from an LDS copy of the table (mixed batch).
 #include "internal.hpp"
+#include "persistent.hpp"
 
 namespace malbec {
 
@@ -95,6 +96,70 @@ __global__ void __launch_bounds__(256) rk4_f64_kernel(IntArgs A, StTable T)
     }
 }
 
+// One lane of the batch as a work item of the persistent driver; the step is the
+// same rk4_step_f64 / terminate_f64 sequence as the one-thread-per-lane kernel.
+struct F64Prog {
+    const IntArgs &A;
+    const Spacetime *table;  // LDS copy (mixed batch) or kernel argument
+    bool multi;
+    int32_t n_st;
+    struct Lane {
+        double y[8];
+        Spacetime S;
+        int32_t st, taken;
+    };
+    __device__ __forceinline__ bool load(int64_t i, Lane &L)
+    {
+        L.st = A.status[i];
+        if (L.st != kActive) return false;
+        int32_t sid = 0;
+        if (multi) {
+            sid = A.st_of_lane[i];
+            if (sid < 0 || sid >= n_st) {
+                A.status[i] = kNonfinite;
+                return false;
+            }
+        }
+        L.S = table[sid];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) L.y[k] = A.state[k * A.n + i];
+        L.taken = 0;
+        return A.n_steps > 0;
+    }
+    __device__ __forceinline__ bool step(Lane &L)
+    {
+        double y1[8], sr[3];
+        rk4_step_f64(L.S, A.h, L.y, y1, sr);
+        ++L.taken;
+        bool accept;
+        L.st = terminate_f64(L.S, A.r_escape, sr, y1, accept);
+        if (accept) {
+#pragma unroll
+            for (int c = 0; c < 8; ++c) L.y[c] = y1[c];
+        }
+        return L.st != kActive || L.taken == A.n_steps;
+    }
+    __device__ __forceinline__ void store(int64_t i, const Lane &L)
+    {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) A.state[k * A.n + i] = L.y[k];
+        A.status[i] = L.st;
+        A.steps[i] += L.taken;
+    }
+};
+
+template <bool MULTI>
+__global__ void __launch_bounds__(256) rk4_f64_persistent_kernel(IntArgs A, StTable T,
+                                                                 unsigned long long *counter,
+                                                                 int32_t chunk)
+{
+    __shared__ Spacetime lds_st[kMaxSt];
+    for (int k = threadIdx.x; k < T.n_st; k += blockDim.x) lds_st[k] = T.st[k];
+    __syncthreads();
+    F64Prog P{A, lds_st, MULTI, T.n_st};
+    persistent_loop(P, A.n, counter, chunk);
+}
+
 template <bool MULTI, bool CKPT>
 int launch_kernel(const IntArgs &A, const StTable &T, int block, hipStream_t s)
 {
@@ -108,7 +173,7 @@ int launch_kernel(const IntArgs &A, const StTable &T, int block, hipStream_t s)
 
 int launch_integrate_f64(const malbec_run &run, const StTable &T, const int32_t *st_of_lane,
                          int64_t n, double *state, int32_t *status, int32_t *steps,
-                         double *checkpoints, hipStream_t s)
+                         double *checkpoints, void *ws, hipStream_t s)
 {
     const int block = run.block > 0 ? run.block : 256;
     if (block > 256) return fail(MALBEC_EINVAL, "block %d exceeds the kernel's launch bound 256", block);
@@ -126,6 +191,29 @@ int launch_integrate_f64(const malbec_run &run, const StTable &T, const int32_t 
     A.r_escape = run.r_escape;
     A.ck_every = run.checkpoint_every;
     A.ck_last = run.checkpoint_every > 0 ? (int32_t)(total / run.checkpoint_every) : 0;
+    if (run.persistent) {
+        if (A.ckpt) return fail(MALBEC_ENOTSUP, "checkpoints need the non-persistent kernel");
+        // one launch runs all steps; steps_per_chunk is the retire/refill interval
+        A.k0 = 0;
+        A.n_steps = (int32_t)total;
+        const int32_t sub = run.steps_per_chunk > 0 ? run.steps_per_chunk : 64;
+        int grid = 0;
+        int rc = persistent_grid(multi ? (const void *)rk4_f64_persistent_kernel<true>
+                                       : (const void *)rk4_f64_persistent_kernel<false>,
+                                 block, n, grid);
+        if (rc) return rc;
+        unsigned long long *counter = (unsigned long long *)ws;
+        hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(1), 0, s, counter);
+        MALBEC_LAUNCH_CHECK("zero_u64_kernel");
+        if (multi)
+            hipLaunchKernelGGL((rk4_f64_persistent_kernel<true>), dim3(grid), dim3(block), 0, s, A, T,
+                               counter, sub);
+        else
+            hipLaunchKernelGGL((rk4_f64_persistent_kernel<false>), dim3(grid), dim3(block), 0, s, A, T,
+                               counter, sub);
+        MALBEC_LAUNCH_CHECK("rk4_f64_persistent_kernel");
+        return MALBEC_OK;
+    }
     for (int64_t k0 = 0; k0 < total; k0 += chunk) {
         A.k0 = (int32_t)k0;
         A.n_steps = (int32_t)((total - k0) < chunk ? (total - k0) : chunk);

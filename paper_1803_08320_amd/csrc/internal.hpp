@@ -46,10 +46,13 @@ int launch_init(const malbec_ic_spec &spec, const StTable &T, const int32_t *st_
                 int64_t n, double *state, double *consts, int64_t *attempts, hipStream_t s);
 int launch_integrate_f64(const malbec_run &run, const StTable &T, const int32_t *st_of_lane,
                          int64_t n, double *state, int32_t *status, int32_t *steps,
-                         double *checkpoints, hipStream_t s);
+                         double *checkpoints, void *ws, hipStream_t s);
 int launch_integrate_f32k(const malbec_run &run, const StTable &T, const int32_t *st_of_lane,
-                          int64_t n, double *state, int32_t *status, int32_t *steps,
+                          int64_t n, double *state, int32_t *status, int32_t *steps, void *ws,
                           hipStream_t s);
+// Grid of a persistent kernel: resident blocks per CU x CUs, capped by the blocks the
+// work needs.
+int persistent_grid(const void *kernel, int block, int64_t n_items, int &grid);
 int launch_camera(const malbec_camera &cam, double r_stop, double disk_r_in, int32_t *status,
                   int32_t *steps, double *hit, double *final_state, void *ws, hipStream_t s);
 int launch_adjoint(const malbec_run &run, const StTable &T, const int32_t *st_of_lane, int64_t n,

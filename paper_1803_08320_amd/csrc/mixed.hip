@@ -9,19 +9,34 @@
 // that starts inside r_zone runs entirely in FP64 on hi + lo and splits the result
 // back.  The double state in HBM is hi + lo at load (split) and at store (sum).
 #include "internal.hpp"
+#include "persistent.hpp"
 
 namespace malbec {
 
 namespace {
 
+// FP32 right-hand side.  Stage 0 takes the library sincosf; later stages rotate that
+// pair by the small angle difference (Taylor terms through d^5 / d^6, truncation
+// below 1e-10 for |d| <= 0.125, far under FP32 rounding).
 struct AccelF32 {
     float M, a;
-    __device__ __forceinline__ void operator()(int, float r, float th, float ut, float ur,
+    float th0, s0, c0;
+    __device__ __forceinline__ void operator()(int stage, float r, float th, float ut, float ur,
                                                float uth, float uph, float &at, float &ar,
-                                               float &ath, float &aph) const
+                                               float &ath, float &aph)
     {
         float s, c;
-        sincosf(th, &s, &c);
+        const float d = th - th0;
+        if (stage == 0 || !(fabsf(d) <= 0.125f)) {
+            sincosf(th, &s, &c);
+            if (stage == 0) { th0 = th; s0 = s; c0 = c; }
+        } else {
+            const float d2 = d * d;
+            const float sd = fmaf(d * d2, fmaf(d2, 1.0f / 120.0f, -1.0f / 6.0f), d);
+            const float cd = fmaf(d2, fmaf(d2, fmaf(d2, -1.0f / 720.0f, 1.0f / 24.0f), -0.5f), 1.0f);
+            s = fmaf(s0, cd, c0 * sd);
+            c = fmaf(c0, cd, -s0 * sd);
+        }
         kerr_accel<float>(M, a, r, s, c, ut, ur, uth, uph, at, ar, ath, aph);
     }
 };
@@ -54,93 +69,127 @@ __device__ __forceinline__ void two_sum(float a, float b, float &s, float &e)
     e = (a - ap) + (b - bp);
 }
 
-template <bool MULTI>
-__global__ void __launch_bounds__(256) rk4_f32k_kernel(MixArgs A, StTable T)
-{
-    __shared__ Spacetime lds_st[kMaxSt];
-    if (MULTI) {
-        for (int k = threadIdx.x; k < T.n_st; k += blockDim.x) lds_st[k] = T.st[k];
-        __syncthreads();
-    }
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= A.n) return;
-    int32_t st = A.status[i];
-    int32_t sid = 0;
-    if (MULTI) {
-        sid = A.st_of_lane[i];
-        if (sid < 0 || sid >= T.n_st) {
-            sid = 0;
-            if (st == kActive) st = kNonfinite;
-            A.status[i] = st;
+// One lane as a work item: load splits the double state, step advances one step
+// (FP64 inside the zone, FP32 + two-sum outside), store recombines hi + lo.
+struct MixProg {
+    const MixArgs &A;
+    const Spacetime *table;
+    bool multi;
+    int32_t n_st;
+    struct Lane {
+        float hi[8], lo[8];
+        Spacetime S;
+        int32_t st, taken;
+    };
+    __device__ __forceinline__ bool load(int64_t i, Lane &L)
+    {
+        L.st = A.status[i];
+        if (L.st != kActive) return false;
+        int32_t sid = 0;
+        if (multi) {
+            sid = A.st_of_lane[i];
+            if (sid < 0 || sid >= n_st) {
+                A.status[i] = kNonfinite;
+                return false;
+            }
         }
-    }
-    if (st != kActive) return;
-    const Spacetime S = MULTI ? lds_st[sid] : T.st[0];
-    AccelF32 f32{(float)S.M, (float)S.a};
-    const float h32 = (float)A.h;
-
-    float hi[8], lo[8];
+        L.S = table[sid];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) split(A.state[k * A.n + i], hi[k], lo[k]);
-    int32_t taken = 0;
-
-    for (int32_t k = 0; k < A.n_steps; ++k) {
-        ++taken;
-        const double r_now = (double)hi[1] + (double)lo[1];
+        for (int k = 0; k < 8; ++k) split(A.state[k * A.n + i], L.hi[k], L.lo[k]);
+        L.taken = 0;
+        return A.n_steps > 0;
+    }
+    __device__ __forceinline__ bool step(Lane &L)
+    {
+        ++L.taken;
+        const Spacetime &S = L.S;
+        const double r_now = (double)L.hi[1] + (double)L.lo[1];
         if (r_now < S.r_zone) {
             double y[8], y1[8], sr[3];
 #pragma unroll
-            for (int c = 0; c < 8; ++c) y[c] = (double)hi[c] + (double)lo[c];
+            for (int c = 0; c < 8; ++c) y[c] = (double)L.hi[c] + (double)L.lo[c];
             rk4_step_f64(S, A.h, y, y1, sr);
             bool accept;
-            st = terminate_f64(S, A.r_escape, sr, y1, accept);
+            L.st = terminate_f64(S, A.r_escape, sr, y1, accept);
             if (accept) {
 #pragma unroll
-                for (int c = 0; c < 8; ++c) split(y1[c], hi[c], lo[c]);
+                for (int c = 0; c < 8; ++c) split(y1[c], L.hi[c], L.lo[c]);
             }
         } else {
+            AccelF32 f32{(float)S.M, (float)S.a, 0.0f, 0.0f, 1.0f};
             float d[8], sr[3];
-            rk4_delta(f32, h32, hi, d, sr);
+            rk4_delta(f32, (float)A.h, L.hi, d, sr);
             if ((double)sr[0] <= S.r_stop || (double)sr[1] <= S.r_stop || (double)sr[2] <= S.r_stop) {
-                st = kHorizon;
+                L.st = kHorizon;
             } else {
                 float nh[8], nl[8];
                 bool ok = true;
 #pragma unroll
                 for (int c = 0; c < 8; ++c) {
-                    two_sum(hi[c], d[c] + lo[c], nh[c], nl[c]);
+                    two_sum(L.hi[c], d[c] + L.lo[c], nh[c], nl[c]);
                     ok = ok && __builtin_isfinite(nh[c]) && __builtin_isfinite(nl[c]);
                 }
                 const double th = (double)nh[2] + (double)nl[2];
                 if (!(ok && th > 0.0 && th < 3.14159265358979323846)) {
-                    st = kNonfinite;
+                    L.st = kNonfinite;
                 } else {
 #pragma unroll
-                    for (int c = 0; c < 8; ++c) { hi[c] = nh[c]; lo[c] = nl[c]; }
-                    const double r1 = (double)hi[1] + (double)lo[1];
-                    if (r1 <= S.r_stop) st = kHorizon;
-                    else if (r1 >= A.r_escape) st = kEscape;
+                    for (int c = 0; c < 8; ++c) { L.hi[c] = nh[c]; L.lo[c] = nl[c]; }
+                    const double r1 = (double)L.hi[1] + (double)L.lo[1];
+                    if (r1 <= S.r_stop) L.st = kHorizon;
+                    else if (r1 >= A.r_escape) L.st = kEscape;
                 }
             }
         }
-        if (st != kActive) break;
+        return L.st != kActive || L.taken == A.n_steps;
     }
+    __device__ __forceinline__ void store(int64_t i, const Lane &L)
+    {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) A.state[k * A.n + i] = (double)hi[k] + (double)lo[k];
-    A.status[i] = st;
-    A.steps[i] += taken;
+        for (int k = 0; k < 8; ++k) A.state[k * A.n + i] = (double)L.hi[k] + (double)L.lo[k];
+        A.status[i] = L.st;
+        A.steps[i] += L.taken;
+    }
+};
+
+template <bool MULTI>
+__global__ void __launch_bounds__(256) rk4_f32k_kernel(MixArgs A, StTable T)
+{
+    __shared__ Spacetime lds_st[kMaxSt];
+    for (int k = threadIdx.x; k < T.n_st; k += blockDim.x) lds_st[k] = T.st[k];
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    MixProg P{A, lds_st, MULTI, T.n_st};
+    MixProg::Lane L;
+    if (!P.load(i, L)) return;
+    while (!P.step(L)) {
+    }
+    P.store(i, L);
+}
+
+template <bool MULTI>
+__global__ void __launch_bounds__(256) rk4_f32k_persistent_kernel(MixArgs A, StTable T,
+                                                                  unsigned long long *counter,
+                                                                  int32_t chunk)
+{
+    __shared__ Spacetime lds_st[kMaxSt];
+    for (int k = threadIdx.x; k < T.n_st; k += blockDim.x) lds_st[k] = T.st[k];
+    __syncthreads();
+    MixProg P{A, lds_st, MULTI, T.n_st};
+    persistent_loop(P, A.n, counter, chunk);
 }
 
 }  // namespace
 
 int launch_integrate_f32k(const malbec_run &run, const StTable &T, const int32_t *st_of_lane,
-                          int64_t n, double *state, int32_t *status, int32_t *steps, hipStream_t s)
+                          int64_t n, double *state, int32_t *status, int32_t *steps, void *ws,
+                          hipStream_t s)
 {
     const int block = run.block > 0 ? run.block : 256;
     if (block > 256) return fail(MALBEC_EINVAL, "block %d exceeds the kernel's launch bound 256", block);
     const bool multi = st_of_lane != nullptr && T.n_st > 1;
     const int64_t total = run.n_steps;
-    const int64_t chunk = run.steps_per_chunk > 0 ? run.steps_per_chunk : total;
     MixArgs A;
     A.n = n;
     A.state = state;
@@ -149,6 +198,27 @@ int launch_integrate_f32k(const malbec_run &run, const StTable &T, const int32_t
     A.st_of_lane = multi ? st_of_lane : nullptr;
     A.h = run.h;
     A.r_escape = run.r_escape;
+    if (run.persistent) {
+        A.n_steps = (int32_t)total;
+        const int32_t sub = run.steps_per_chunk > 0 ? run.steps_per_chunk : 64;
+        int grid = 0;
+        int rc = persistent_grid(multi ? (const void *)rk4_f32k_persistent_kernel<true>
+                                       : (const void *)rk4_f32k_persistent_kernel<false>,
+                                 block, n, grid);
+        if (rc) return rc;
+        unsigned long long *counter = (unsigned long long *)ws;
+        hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(1), 0, s, counter);
+        MALBEC_LAUNCH_CHECK("zero_u64_kernel");
+        if (multi)
+            hipLaunchKernelGGL((rk4_f32k_persistent_kernel<true>), dim3(grid), dim3(block), 0, s, A, T,
+                               counter, sub);
+        else
+            hipLaunchKernelGGL((rk4_f32k_persistent_kernel<false>), dim3(grid), dim3(block), 0, s, A,
+                               T, counter, sub);
+        MALBEC_LAUNCH_CHECK("rk4_f32k_persistent_kernel");
+        return MALBEC_OK;
+    }
+    const int64_t chunk = run.steps_per_chunk > 0 ? run.steps_per_chunk : total;
     for (int64_t k0 = 0; k0 < total; k0 += chunk) {
         A.n_steps = (int32_t)((total - k0) < chunk ? (total - k0) : chunk);
         if (multi)

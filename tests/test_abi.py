@@ -49,7 +49,7 @@ def test_struct_layout_matches_header(m, tmp_path):
                    "#define O(T, f) printf(#T \".\" #f \" %zu\\n\", offsetof(T, f));\n"
                    "int main(void){P(malbec_spacetime)P(malbec_batch)P(malbec_ic_spec)"
                    "P(malbec_run)P(malbec_camera)O(malbec_ic_spec, rows)O(malbec_ic_spec, max_attempts)"
-                   "O(malbec_run, checkpoint_every)O(malbec_camera, max_steps)O(malbec_camera, persistent)"
+                   "O(malbec_run, checkpoint_every)O(malbec_run, persistent)O(malbec_camera, max_steps)O(malbec_camera, persistent)"
                    "O(malbec_batch, st_of_lane)return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
@@ -63,6 +63,7 @@ def test_struct_layout_matches_header(m, tmp_path):
     assert int(got["malbec_ic_spec.rows"]) == m.c_ic_spec.rows.offset
     assert int(got["malbec_ic_spec.max_attempts"]) == m.c_ic_spec.max_attempts.offset
     assert int(got["malbec_run.checkpoint_every"]) == m.c_run.checkpoint_every.offset
+    assert int(got["malbec_run.persistent"]) == m.c_run.persistent.offset
     assert int(got["malbec_camera.max_steps"]) == m.c_camera.max_steps.offset
     assert int(got["malbec_camera.persistent"]) == m.c_camera.persistent.offset
     assert int(got["malbec_batch.st_of_lane"]) == m.c_batch.st_of_lane.offset
@@ -75,7 +76,7 @@ def _batch(m, sts=((1.0, 0.9),)):
 
 def _run(m, **kw):
     d = dict(h=0.02, n_steps=10, precision=0, block=0, horizon_factor=1.01, r_escape=1500.0,
-             fp64_zone_factor=1.2, steps_per_chunk=0, checkpoint_every=0)
+             fp64_zone_factor=1.2, steps_per_chunk=0, checkpoint_every=0, persistent=0, pad_=0)
     d.update(kw)
     return m.c_run(**d)
 
@@ -95,6 +96,8 @@ FAKE = C.c_void_p(0x1000)  # never dereferenced: every case below fails validati
     (dict(block=100), ((1.0, 0.9),), 4, -1),
     (dict(), ((1.0, 0.9),), -3, -1),         # n < 0
     (dict(checkpoint_every=4), ((1.0, 0.9),), 4, -1),  # no checkpoint buffer
+    (dict(persistent=2), ((1.0, 0.9),), 4, -1),
+    (dict(persistent=1), ((1.0, 0.9),), 4, -2),        # persistent needs a workspace
 ])
 def test_integrate_argument_errors(m, kw, sts, n, expect):
     run = _run(m, **kw)

@@ -106,3 +106,35 @@ def test_mixed_statuses_and_inactive_lanes(m, orc):
     # the split hi + lo of an untouched double is exact to ~48 bits
     ref = orc.integrate(st, s0[:, 2:], 0.02, 10)
     assert mixed_rel(out[:, 2:], ref[0]).max() < 1e-5
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32k"])
+@pytest.mark.parametrize("chunk", [1, 16, 64])
+def test_persistent_equals_plain_bitwise(m, orc, precision, chunk):
+    """The persistent kernel (refilling lanes that plunge early) gives the same bits as
+    one thread per lane, on a 16-spin batch where low spins plunge often."""
+    per = 300
+    n = 16 * per + 5
+    st_of_lane = np.concatenate([np.repeat(np.arange(16), per), np.arange(5)]).astype(np.int32)
+    rc, s0, _, _ = orc.ic_constants(4, SPINS, n, KERR_RANGES, st_of_lane=st_of_lane)
+    status = np.zeros(n, np.int32)
+    status[7] = 2  # an inactive lane stays untouched
+    kw = dict(st_of_lane=st_of_lane, precision=precision, fp64_zone_factor=1.2)
+    import torch
+
+    def go(persistent):
+        state = torch.as_tensor(np.ascontiguousarray(s0)).cuda()
+        stt = torch.as_tensor(status).cuda()
+        spp = torch.zeros(n, dtype=torch.int32, device="cuda")
+        m.integrate(state, stt, spp, SPINS, h=0.02, n_steps=3000, persistent=persistent,
+                    steps_per_chunk=chunk if persistent else 0,
+                    st_of_lane=torch.as_tensor(st_of_lane).cuda(), precision=precision,
+                    fp64_zone_factor=1.2)
+        torch.cuda.synchronize()
+        return state.cpu().numpy(), stt.cpu().numpy(), spp.cpu().numpy()
+
+    a, b = go(False), go(True)
+    assert (a[1] == 1).sum() > 200  # plunging lanes exist
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    assert b[1][7] == 2 and b[2][7] == 0 and np.array_equal(b[0][:, 7], s0[:, 7])
