@@ -42,6 +42,8 @@ def parse():
                    help="oracle sample: this many strided lanes x the full step count")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-f32k", action="store_true", help="skip the FP32-compensated leg")
+    p.add_argument("--no-extra", action="store_true",
+                   help="skip the camera, mixed-spin batch and adjoint legs")
     p.add_argument("--probe-copy-bytes", type=int, default=0,
                    help="first run one device-to-device copy of this many bytes (a plain copy "
                         "kernel of known size, used to calibrate HBM byte counters)")
@@ -191,6 +193,9 @@ def main():
                           "pos_err_vs_f64_p99": float(np.quantile(pos, 0.99)),
                           "status_agree_frac": float(((status == st64).float().mean()).item())}
 
+    if not args.no_extra:
+        result["extra"] = extra_legs(m, torch, np)
+
     if not args.no_cpu_baseline:
         import oracle
         k = max(1, n // args.cpu_lanes)
@@ -207,6 +212,92 @@ def main():
                                   "sample": "%d strided lanes of the workload x %d RK4 steps "
                                             "(%.1f s wall)" % (len(idx), n_rk, dt)}
     print(json.dumps(result))
+
+
+def _timed(torch, fn):
+    fn()  # warm-up
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t
+
+
+def extra_legs(m, torch, np):
+    """One timed run (after a warm-up) of each remaining hot-path configuration."""
+    out = {}
+    # camera: a = 0.998, r_obs = 1000 M, i = 60 deg, 2048 x 2048 pixels over +-25 M
+    for persistent in (1, 0):
+        cam = m.Camera(nx=2048, ny=2048, persistent=persistent)
+        res = {}
+
+        def run_cam():
+            res["o"] = m.trace_camera(cam)
+        dt = _timed(torch, run_cam)
+        st = res["o"]["status"]
+        ls = int(res["o"]["steps"].sum().item())
+        key = "camera_persistent" if persistent else "camera_plain"
+        out[key] = {"lane_steps_per_s": ls / dt, "rays_per_s": st.numel() / dt, "ms": 1e3 * dt,
+                    "status_counts": [int(x) for x in torch.bincount(st, minlength=6).cpu()]}
+    out["camera_persistent"]["speedup_vs_plain"] = (out["camera_persistent"]["lane_steps_per_s"] /
+                                                    out["camera_plain"]["lane_steps_per_s"])
+
+    # mixed-spin batch: 16 spins a_k = 0.99 k / 15 x 262,144 lanes, FP32 compensated state,
+    # FP64 within 1.2 r_+, 20,000 steps; persistent refill vs one thread per lane, and FP64
+    spins = [(1.0, 0.99 * k / 15) for k in range(16)]
+    n = 16 * 262144
+    sol = torch.arange(16, device="cuda", dtype=torch.int32).repeat_interleave(262144)
+    s0, c0, _ = m.init_particles(m.ICSpec(mode=m.IC_CONSTANTS, seed=4), spins, n, st_of_lane=sol)
+    state = torch.empty_like(s0)
+    status, steps = m.new_lane_arrays(n)
+    inv = torch.empty((4, n), dtype=torch.float64, device="cuda")
+    for name, kw in (("mixed_f32k_persistent", dict(precision="f32k", persistent=True)),
+                     ("mixed_f32k_plain", dict(precision="f32k", persistent=False)),
+                     ("mixed_f64_persistent", dict(precision="f64", persistent=True))):
+        def run_mix():
+            state.copy_(s0)
+            status.zero_()
+            steps.zero_()
+            m.integrate(state, status, steps, spins, h=0.02, n_steps=20000, st_of_lane=sol,
+                        fp64_zone_factor=1.2, **kw)
+        dt = _timed(torch, run_mix)
+        ls = int(steps.sum().item())
+        out[name] = {"lane_steps_per_s": ls / dt, "ms": 1e3 * dt,
+                     "plunged_frac": float((status == 1).float().mean().item())}
+        if name == "mixed_f32k_persistent":
+            m.invariants(state, spins, st_of_lane=sol, out=inv)
+            act = (status == 0)
+            q_ok = act & (c0[2] >= 0.1)
+            dQ = ((inv[2] / c0[2] - 1).abs())[q_ok]
+            dE = ((inv[0] / c0[0] - 1).abs())[act]
+            out[name]["dQ_over_Q_p99"] = float(torch.quantile(dQ[:1 << 20], 0.99).item())
+            out[name]["dE_over_E_p99"] = float(torch.quantile(dE[:1 << 20], 0.99).item())
+    # adjoint: a = 0.7, 65,536 lanes, 8,192 steps, checkpoints every 256
+    st7 = (1.0, 0.7)
+    n, N, K = 65536, 8192, 256
+    y0, c7, _ = m.init_particles(m.ICSpec(mode=m.IC_CONSTANTS, seed=5), [st7], n)
+    p = torch.stack([y0[1], y0[2], y0[5], y0[6], c7[1]]).contiguous().requires_grad_(True)
+    E = c7[0].contiguous()
+    tgt = torch.stack([y0[1], y0[2], torch.zeros_like(y0[1])]) + 0.5
+    times = {}
+
+    def fwd_bwd():
+        p.grad = None
+        a = time.perf_counter()
+        yN, st_, sp_ = m.IntegrateFromParams.apply(p, E, st7, 0.02, N, K)
+        loss = ((yN[1:4] - tgt) ** 2).sum()
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        times["fwd"], times["bwd"] = b - a, time.perf_counter() - b
+        times["ls"] = int(sp_.sum().item())
+    fwd_bwd()
+    fwd_bwd()
+    out["adjoint"] = {"forward_ms": 1e3 * times["fwd"], "backward_ms": 1e3 * times["bwd"],
+                      "backward_over_forward": times["bwd"] / times["fwd"],
+                      "gradient_lane_steps_per_s": times["ls"] / (times["fwd"] + times["bwd"])}
+    return out
 
 
 if __name__ == "__main__":

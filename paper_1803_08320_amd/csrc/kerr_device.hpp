@@ -17,9 +17,11 @@ struct Spacetime {
     double r_zone;        // F32_KAHAN: r below which steps run in FP64
 };
 
-// sin and cos of theta + d from those of theta, for |d| <= kRotMax: Taylor
-// polynomials of sin d (through d^9) and cos d (through d^10), whose truncation is
-// below 3e-18 there, and the angle-addition formulas.
+// sin and cos of theta + d from those of theta, for |d| <= kRotMax and
+// |d| <= sin(theta) / 2: Taylor polynomials of sin d (through d^9) and cos d (through
+// d^10), whose truncation is below 3e-18 there, and the angle-addition formulas
+// (about 2 ulp; the second bound keeps sin(theta + d) >= sin(theta) / 2, so the
+// addition does not cancel).
 constexpr double kRotMax = 0.125;
 
 __device__ __forceinline__ void rotate(double s0, double c0, double d, double &s, double &c)
@@ -38,9 +40,45 @@ __device__ __forceinline__ void rotate(double s0, double c0, double d, double &s
     c = fma(c0, cd, -s0 * sd);
 }
 
+// sin and cos of theta in (0, pi) (every accepted state has theta there): Cody-Waite
+// reduction x = theta - k pi/2, k = rint(theta / (pi/2)) in {0, 1, 2}, with pi/2 split
+// in two parts so that k * kPio2Hi is exact, then the Taylor series of sin x through
+// x^17 and cos x through x^18 on |x| <= pi/4 (truncation below 1e-19), then the
+// quadrant swap.
+__device__ __forceinline__ void sincos_0pi(double th, double &s, double &c)
+{
+    constexpr double kPio2Hi = 1.5707963267341256e+00;  // 33 significant bits of pi/2
+    constexpr double kPio2Lo = 6.0771005065061922e-11;  // pi/2 - kPio2Hi
+    constexpr double k2OverPi = 0.63661977236758134308;
+    const double k = rint(th * k2OverPi);
+    const double x = fma(-k, kPio2Lo, fma(-k, kPio2Hi, th));
+    const double x2 = x * x;
+    double ps = fma(x2, 1.0 / 355687428096000.0, -1.0 / 1307674368000.0);  // x^17, x^15
+    ps = fma(x2, ps, 1.0 / 6227020800.0);
+    ps = fma(x2, ps, -1.0 / 39916800.0);
+    ps = fma(x2, ps, 1.0 / 362880.0);
+    ps = fma(x2, ps, -1.0 / 5040.0);
+    ps = fma(x2, ps, 1.0 / 120.0);
+    ps = fma(x2, ps, -1.0 / 6.0);
+    const double sx = fma(x * x2, ps, x);
+    double pc = fma(x2, 1.0 / 6402373705728000.0, -1.0 / 20922789888000.0);  // x^18, x^16
+    pc = fma(x2, pc, 1.0 / 87178291200.0);
+    pc = fma(x2, pc, -1.0 / 479001600.0);
+    pc = fma(x2, pc, 1.0 / 3628800.0);
+    pc = fma(x2, pc, -1.0 / 40320.0);
+    pc = fma(x2, pc, 1.0 / 720.0);
+    pc = fma(x2, pc, -1.0 / 24.0);
+    pc = fma(x2, pc, 0.5);
+    const double cx = fma(-x2, pc, 1.0);
+    // k = 0: (sx, cx); k = 1: (cx, -sx); k = 2: (-sx, -cx)
+    s = k == 1.0 ? cx : (k == 0.0 ? sx : -sx);
+    c = k == 1.0 ? -sx : (k == 0.0 ? cx : -cx);
+}
+
 // FP64 geodesic right-hand side as a functor for rk4_stages.  Stage 0 evaluates
-// sincos(theta); the later stages of the same step, whose theta differs from the
-// stage-0 theta by an exactly computed small d, rotate that pair instead.
+// sin and cos of theta; the later stages of the same step, whose theta differs from
+// the stage-0 theta by an exactly computed small d, rotate that pair instead (the
+// library sincos if |d| > kRotMax).
 struct AccelF64 {
     double M, a;
     double th0, s0, c0;
@@ -50,9 +88,15 @@ struct AccelF64 {
     {
         double s, c;
         const double d = th - th0;
-        if (stage == 0 || !(fabs(d) <= kRotMax)) {
+        if (stage == 0) {
+            sincos_0pi(th, s, c);
+            th0 = th;
+            s0 = s;
+            c0 = c;
+        } else if (!(fabs(d) <= kRotMax && fabs(d) <= 0.5 * s0)) {
+            // large step, or a step that brings theta close to a pole, where the
+            // rotation's cancellation would cost relative accuracy in sin theta
             sincos(th, &s, &c);
-            if (stage == 0) { th0 = th; s0 = s; c0 = c; }
         } else {
             rotate(s0, c0, d, s, c);
         }

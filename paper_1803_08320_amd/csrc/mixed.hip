@@ -27,7 +27,7 @@ struct AccelF32 {
     {
         float s, c;
         const float d = th - th0;
-        if (stage == 0 || !(fabsf(d) <= 0.125f)) {
+        if (stage == 0 || !(fabsf(d) <= 0.125f && fabsf(d) <= 0.5f * s0)) {
             sincosf(th, &s, &c);
             if (stage == 0) { th0 = th; s0 = s; c0 = c; }
         } else {
