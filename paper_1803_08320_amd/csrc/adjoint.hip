@@ -43,14 +43,9 @@ __device__ __forceinline__ void vjp_accel(double M, double a, double r, double t
     typedef Dual2<double> D;
     double s, c;
     sincos(th, &s, &c);
-    KerrCoef<D> Kd;
-    kerr_coef<D>(D(M), D(a), D(r, 1.0, 0.0), D(s, 0.0, c), D(c, 0.0, -s), Kd);
+    // pass 1: primal coefficients -> contraction -> cotangents of the coefficients
     KerrCoef<double> K;
-#define MALBEC_V(f) K.f = Kd.f.v;
-    MALBEC_V(r) MALBEC_V(gtt) MALBEC_V(gtp) MALBEC_V(gpp) MALBEC_V(iDs2) MALBEC_V(irho2)
-    MALBEC_V(Dirho2) MALBEC_V(a2sc) MALBEC_V(dgtt_r) MALBEC_V(dgtt_th) MALBEC_V(dgtp_r)
-    MALBEC_V(dgtp_th) MALBEC_V(dgpp_r) MALBEC_V(dgpp_th) MALBEC_V(dgrr_r) MALBEC_V(dgrr_th)
-#undef MALBEC_V
+    kerr_coef<double>(M, a, r, s, c, K);
     double at, ar, ath, aph;
     KerrContr<double> X;
     kerr_contract(K, ut, ur, uth, uph, at, ar, ath, aph, &X);
@@ -109,7 +104,10 @@ __device__ __forceinline__ void vjp_accel(double M, double a, double r, double t
     ubar[1] = bur;
     ubar[2] = buth;
     ubar[3] = buph;
-    // chain through the coefficients' r and theta derivatives
+    // pass 2: the coefficients again in dual numbers (d/dr, d/dtheta), each folded into
+    // the r and theta cotangents as soon as it is formed
+    KerrCoef<D> Kd;
+    kerr_coef<D>(D(M), D(a), D(r, 1.0, 0.0), D(s, 0.0, c), D(c, 0.0, -s), Kd);
     double sr = 0.0, st = 0.0;
 #define MALBEC_C(f) sr = fma(B.f, Kd.f.dr, sr); st = fma(B.f, Kd.f.dth, st);
     MALBEC_C(r) MALBEC_C(gtt) MALBEC_C(gtp) MALBEC_C(gpp) MALBEC_C(iDs2) MALBEC_C(irho2)
