@@ -29,6 +29,33 @@ if ROOT not in sys.path:
 
 PEAK_FP64_VECTOR_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 128 FP64 flop/clk/CU
 
+# HBM traffic of one rk4_f64_kernel launch of this workload, from rocprofv3 counter
+# runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by the ratio of a
+# plain 1 GiB device copy's known bytes to what the same counter reads for it.  The
+# figures hold for the kernel sources whose SHA-256 is given; after any change to
+# them the traffic is reported as null until the counters are taken again.
+KERNEL_SOURCES = ("integrate.hip", "kerr_device.hpp", "kerr_accel.hpp", "internal.hpp",
+                  "persistent.hpp")
+TRAFFIC = {"sources_sha256": "7f491b5364a63d0c6dbfd59931b3e1dfb2e88d3895a6e5ce5f0ce2099ef25616",
+           "fetch_kib": 36985.5, "fetch_scale": 1048576 / 524315.6875,
+           "write_kib": 73728.0, "write_scale": 1048576 / 1048576.0}
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1803_08320_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic_bytes():
+    t = TRAFFIC
+    if t["sources_sha256"] is None or t["sources_sha256"] != kernel_sources_sha256():
+        return None
+    return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
+
 
 def parse():
     p = argparse.ArgumentParser(description=__doc__.split("\n")[0])
@@ -38,7 +65,7 @@ def parse():
     p.add_argument("--lanes", type=int, default=1 << 20)
     p.add_argument("--rk-steps", type=int, default=20000)
     p.add_argument("--block", type=int, default=0)
-    p.add_argument("--cpu-lanes", type=int, default=1024,
+    p.add_argument("--cpu-lanes", type=int, default=12288,
                    help="oracle sample: this many strided lanes x the full step count")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-f32k", action="store_true", help="skip the FP32-compensated leg")
@@ -140,7 +167,8 @@ def main():
                    "block": args.block or 256},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR_TFLOPS,
-                     "traffic": None, "kernel": "rk4_f64_kernel",
+                     "traffic": measured_traffic_bytes(), "kernel": "rk4_f64_kernel",
+                     "algorithmic_bytes": 144.0 * n,
                      "flops_per_lane_step": m.FLOPS_PER_STEP_F64,
                      "kernel_ms_avg": 1e3 * avg_kern_s},
         "physics": {"active_frac": float(act.mean()),

@@ -37,7 +37,7 @@ MAX_SPACETIMES = 64
 
 # Algorithmic FP64 flops of one RK4 step of one lane as implemented (static count of
 # csrc/kerr_accel.hpp by csrc/flopcount.cpp: add/sub/mul/div 1, fma 2, sincos 2).
-FLOPS_PER_STEP_F64 = 570
+FLOPS_PER_STEP_F64 = 534
 
 
 class MalbecError(RuntimeError):

@@ -51,32 +51,29 @@ __device__ __forceinline__ void vjp_accel(double M, double a, double r, double t
     kerr_contract(K, ut, ur, uth, uph, at, ar, ath, aph, &X);
 
     KerrCoef<double> B;  // dL/d(coefficient)
-    // at = iDs2 (gpp Wt - gtp Wp), aph = iDs2 (gtt Wp - gtp Wt)
-    const double X1 = fma(K.gpp, X.Wt, -K.gtp * X.Wp);
-    const double X2 = fma(K.gtt, X.Wp, -K.gtp * X.Wt);
-    B.iDs2 = fma(b_at, X1, b_aph * X2);
-    const double g1 = b_at * K.iDs2, g2 = b_aph * K.iDs2;
-    B.gpp = g1 * X.Wt;
-    B.gtp = -fma(g1, X.Wp, g2 * X.Wt);
-    B.gtt = g2 * X.Wp;
-    const double bWt = fma(g1, K.gpp, -g2 * K.gtp);
-    const double bWp = fma(g2, K.gtt, -g1 * K.gtp);
+    // at = Rtt Wt - Rtp Wp, aph = Rpp Wp - Rtp Wt
+    B.Rtt = b_at * X.Wt;
+    B.Rtp = -fma(b_at, X.Wp, b_aph * X.Wt);
+    B.Rpp = b_aph * X.Wp;
+    const double bWt = fma(b_at, K.Rtt, -b_aph * K.Rtp);
+    const double bWp = fma(b_aph, K.Rpp, -b_at * K.Rtp);
     // ar = Fr Dirho2, ath = Fth irho2
     const double bFr = b_ar * K.Dirho2;
     B.Dirho2 = b_ar * X.Fr;
     const double bFth = b_ath * K.irho2;
     B.irho2 = b_ath * X.Fth;
     // Fr = (Qr - dgrr_r urur)/2 + r uthuth - dgrr_th uruth
-    // Fth = (Qth + dgrr_th urur)/2 + a2sc uthuth - 2 r uruth
+    // Fth = (Qth + dgrr_th urur)/2 + a2sc uthuth - twor uruth
     const double urur = ur * ur, uthuth = uth * uth, uruth = ur * uth;
     const double bQr = 0.5 * bFr, bQth = 0.5 * bFth;
     B.dgrr_r = -0.5 * bFr * urur;
     B.dgrr_th = fma(0.5 * bFth, urur, -bFr * uruth);
-    B.r = fma(bFr, uthuth, -2.0 * bFth * uruth);
+    B.r = bFr * uthuth;
+    B.twor = -bFth * uruth;
     B.a2sc = bFth * uthuth;
     const double burur = 0.5 * fma(bFth, K.dgrr_th, -bFr * K.dgrr_r);
     const double buthuth = fma(bFr, K.r, bFth * K.a2sc);
-    const double buruth = -fma(bFr, K.dgrr_th, 2.0 * bFth * K.r);
+    const double buruth = -fma(bFr, K.dgrr_th, bFth * K.twor);
     double bur = fma(2.0 * ur, burur, uth * buruth);
     double buth = fma(2.0 * uth, buthuth, ur * buruth);
     // Qr = ut Pt_r + uph Pp_r, Qth = ut Pt_th + uph Pp_th
@@ -110,7 +107,7 @@ __device__ __forceinline__ void vjp_accel(double M, double a, double r, double t
     kerr_coef<D>(D(M), D(a), D(r, 1.0, 0.0), D(s, 0.0, c), D(c, 0.0, -s), Kd);
     double sr = 0.0, st = 0.0;
 #define MALBEC_C(f) sr = fma(B.f, Kd.f.dr, sr); st = fma(B.f, Kd.f.dth, st);
-    MALBEC_C(r) MALBEC_C(gtt) MALBEC_C(gtp) MALBEC_C(gpp) MALBEC_C(iDs2) MALBEC_C(irho2)
+    MALBEC_C(r) MALBEC_C(twor) MALBEC_C(Rtt) MALBEC_C(Rtp) MALBEC_C(Rpp) MALBEC_C(irho2)
     MALBEC_C(Dirho2) MALBEC_C(a2sc) MALBEC_C(dgtt_r) MALBEC_C(dgtt_th) MALBEC_C(dgtp_r)
     MALBEC_C(dgtp_th) MALBEC_C(dgpp_r) MALBEC_C(dgpp_th) MALBEC_C(dgrr_r) MALBEC_C(dgrr_th)
 #undef MALBEC_C
@@ -239,10 +236,14 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjArgs A, StTable T)
         sincos(th0, &s0, &c0);
         KerrCoef<D> Kd;
         kerr_coef<D>(D(S.M), D(S.a), D(r0, 1.0, 0.0), D(s0, 0.0, c0), D(c0, 0.0, -s0), Kd);
-        const D itt = -(Kd.gpp * Kd.iDs2), itp = Kd.gtp * Kd.iDs2, ipp = -(Kd.gtt * Kd.iDs2);
+        // inverse (t, phi) block: g^tt = -Rtt, g^tphi = Rtp, g^phiphi = -Rpp
+        const D itt = -Kd.Rtt, itp = Kd.Rtp, ipp = -Kd.Rpp;
         const double ut0 = A.ckpt[4 * n + i], uph0 = A.ckpt[7 * n + i];
-        const double E = A.E_fixed ? A.E_fixed[i] : -(Kd.gtt.v * ut0 + Kd.gtp.v * uph0);
-        const double Lz = fma(Kd.gtp.v, ut0, Kd.gpp.v * uph0);
+        // lower with the block itself: G = inverse of the inverse block
+        const double det = itt.v * ipp.v - itp.v * itp.v;
+        const double gtt = ipp.v / det, gtp = -itp.v / det, gpp = itt.v / det;
+        const double E = A.E_fixed ? A.E_fixed[i] : -(gtt * ut0 + gtp * uph0);
+        const double Lz = fma(gtp, ut0, gpp * uph0);
         // u^t = itt (-E) + itp Lz, u^phi = itp (-E) + ipp Lz
         const double dut_r = fma(itt.dr, -E, itp.dr * Lz), dut_th = fma(itt.dth, -E, itp.dth * Lz);
         const double duph_r = fma(itp.dr, -E, ipp.dr * Lz), duph_th = fma(itp.dth, -E, ipp.dth * Lz);

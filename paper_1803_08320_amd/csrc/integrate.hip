@@ -34,6 +34,12 @@ __device__ __forceinline__ void put_slot(const IntArgs &A, int64_t i, int32_t sl
     for (int k = 0; k < 8; ++k) base[k * A.n + i] = y[k];
 }
 
+__device__ __forceinline__ void copy8(double dst[8], const double src[8])
+{
+#pragma unroll
+    for (int c = 0; c < 8; ++c) dst[c] = src[c];
+}
+
 template <bool MULTI, bool CKPT>
 __global__ void __launch_bounds__(256) rk4_f64_kernel(IntArgs A, StTable T)
 {
@@ -63,7 +69,33 @@ __global__ void __launch_bounds__(256) rk4_f64_kernel(IntArgs A, StTable T)
     int32_t next_slot = 0;
     if (CKPT) next_slot = (A.k0 + A.ck_every - 1) / A.ck_every;  // first slot at or after k0
 
-    if (st == kActive) {
+    if (!CKPT && st == kActive) {
+        // Two steps per iteration, the second with the roles of y and y1 swapped, so
+        // that an accepted step never copies the state.
+        double y1[8];
+        while (taken < A.n_steps) {
+            double sr[3];
+            bool accept;
+            rk4_step_f64(S, A.h, y, y1, sr);
+            ++taken;
+            st = terminate_f64(S, A.r_escape, sr, y1, accept);
+            if (st != kActive || taken == A.n_steps) {
+                if (accept) copy8(y, y1);
+                break;
+            }
+            rk4_step_f64(S, A.h, y1, y, sr);
+            ++taken;
+            st = terminate_f64(S, A.r_escape, sr, y, accept);
+            if (st != kActive) {
+                if (!accept) copy8(y, y1);
+                break;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) A.state[k * A.n + i] = y[k];
+        A.status[i] = st;
+        A.steps[i] += taken;
+    } else if (st == kActive) {
         for (int32_t k = 0; k < A.n_steps; ++k) {
             if (CKPT && (A.k0 + k) == next_slot * A.ck_every) {
                 put_slot(A, i, next_slot, y);
@@ -74,10 +106,7 @@ __global__ void __launch_bounds__(256) rk4_f64_kernel(IntArgs A, StTable T)
             ++taken;
             bool accept;
             st = terminate_f64(S, A.r_escape, sr, y1, accept);
-            if (accept) {
-#pragma unroll
-                for (int c = 0; c < 8; ++c) y[c] = y1[c];
-            }
+            if (accept) copy8(y, y1);
             if (st != kActive) break;
         }
 #pragma unroll
@@ -133,10 +162,7 @@ struct F64Prog {
         ++L.taken;
         bool accept;
         L.st = terminate_f64(L.S, A.r_escape, sr, y1, accept);
-        if (accept) {
-#pragma unroll
-            for (int c = 0; c < 8; ++c) L.y[c] = y1[c];
-        }
+        if (accept) copy8(L.y, y1);
         return L.st != kActive || L.taken == A.n_steps;
     }
     __device__ __forceinline__ void store(int64_t i, const Lane &L)

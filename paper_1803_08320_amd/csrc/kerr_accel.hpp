@@ -49,12 +49,14 @@ MALBEC_HD inline float recip(float x)
 #endif
 }
 
-// Position-dependent coefficients of the acceleration at (r, theta): the metric
-// components that enter the raising, the partial derivatives of the metric, and
-// a few products, with s = sin theta, c = cos theta.
+// Position-dependent coefficients of the acceleration at (r, theta), with
+// s = sin theta, c = cos theta: the raising coefficients of the (t, phi) block
+// (Rtt = g_pp / (Delta s^2), Rtp = g_tp / (Delta s^2), Rpp = g_tt / (Delta s^2), the
+// inverse block being -[[Rtt, -Rtp], [-Rtp, Rpp]]), 1/rho^2, Delta/rho^2, the r and
+// theta partial derivatives of the metric, and a few products.
 template <typename T>
 struct KerrCoef {
-    T r, gtt, gtp, gpp, iDs2, irho2, Dirho2, a2sc;
+    T r, twor, Rtt, Rtp, Rpp, irho2, Dirho2, a2sc;
     T dgtt_r, dgtt_th, dgtp_r, dgtp_th, dgpp_r, dgpp_th, dgrr_r, dgrr_th;
 };
 
@@ -62,43 +64,48 @@ template <typename T>
 MALBEC_HD inline void kerr_coef(T M, T a, T r, T s, T c, KerrCoef<T> &K)
 {
     const T a2 = a * a;
+    const T m2 = T(2) * M;
     const T s2 = s * s;
     const T sc = s * c;
     const T r2 = r * r;
-    const T rho2 = fma(a2, c * c, r2);
-    const T Delta = fma(r, r - T(2) * M, a2);
-    const T inv = recip(rho2 * Delta * s2);
-    const T iDs2 = inv * rho2;          // 1 / (Delta s^2)
-    const T irho2 = inv * (Delta * s2); // 1 / rho^2
-    const T iDelta = iDs2 * s2;         // 1 / Delta
+    const T A = r2 + a2;                    // r^2 + a^2
+    const T rho2 = fma(a2, c * c, r2);      // r^2 + a^2 cos^2
+    const T Delta = fma(-m2, r, A);         // r^2 - 2 M r + a^2
+    const T inv = recip(rho2 * Delta * s2); // 1 / (rho^2 Delta s^2)
+    const T iDs2 = inv * rho2;              // 1 / (Delta s^2)
+    const T irho2 = inv * (Delta * s2);     // 1 / rho^2
+    const T iDelta = iDs2 * s2;             // 1 / Delta
 
-    const T q = T(2) * M * r * irho2;
-    const T A = r2 + a2;
-    const T gpp_over_s2 = fma(a2 * q, s2, A);
+    const T m2i = m2 * irho2;
+    const T q = m2i * r;                    // 2 M r / rho^2;  g_tt = q - 1
+    const T qs2 = q * s2;                   // g_tp = -a q s^2
+    const T gpp_os2 = fma(a2, qs2, A);      // g_pp = (r^2 + a^2 + a^2 q s^2) s^2
 
     // partial derivatives of q and of q s^2
-    const T dq_r = T(2) * M * irho2 * fma(T(-2) * r2, irho2, T(1));
-    const T twosc = T(2) * sc;
-    const T dq_th = q * a2 * twosc * irho2;
-    const T dqs2_th = fma(dq_th, s2, q * twosc);
+    const T dq_r = m2i * fma(T(-2), r2 * irho2, T(1));
+    const T sc2 = sc + sc;
+    const T a2sc = a2 * sc;
+    const T dq_th = (q * irho2) * (a2sc + a2sc);
+    const T dqs2_th = fma(dq_th, s2, q * sc2);
+    const T twor = r + r;
     const T grr = rho2 * iDelta;
 
     K.r = r;
-    K.gtt = q - T(1);
-    K.gtp = -a * q * s2;
-    K.gpp = gpp_over_s2 * s2;
-    K.iDs2 = iDs2;
+    K.twor = twor;
+    K.Rtt = iDelta * gpp_os2;
+    K.Rtp = (-a * q) * iDelta;
+    K.Rpp = iDs2 * (q - T(1));
     K.irho2 = irho2;
     K.Dirho2 = Delta * irho2;
-    K.a2sc = a2 * sc;
+    K.a2sc = a2sc;
     K.dgtt_r = dq_r;
     K.dgtt_th = dq_th;
-    K.dgtp_r = -a * s2 * dq_r;
+    K.dgtp_r = (-a * s2) * dq_r;
     K.dgtp_th = -a * dqs2_th;
-    K.dgpp_r = fma(a2 * s2, dq_r, T(2) * r) * s2;
-    K.dgpp_th = fma(a2 * dqs2_th, s2, gpp_over_s2 * twosc);
-    K.dgrr_r = iDelta * fma(-grr, T(2) * (r - M), T(2) * r);
-    K.dgrr_th = -a2 * twosc * iDelta;
+    K.dgpp_r = fma(-a, K.dgtp_r, twor) * s2;                       // (2r + a^2 s^2 dq_r) s^2
+    K.dgpp_th = fma(-a * K.dgtp_th, s2, gpp_os2 * sc2);            // a^2 d(q s^2) s^2 + g_pp/s^2 2sc
+    K.dgrr_r = iDelta * fma(-grr, twor - m2, twor);                // (2r - g_rr (2r - 2M)) / Delta
+    K.dgrr_th = -(a2sc + a2sc) * iDelta;                           // -2 a^2 s c / Delta
 }
 
 // Intermediate products of the contraction (kept for the adjoint).
@@ -127,11 +134,11 @@ MALBEC_HD inline void kerr_contract(const KerrCoef<T> &K, T ut, T ur, T uth, T u
     // F_r = Qr/2 + r uth^2 - dgrr_r ur^2 / 2 - dgrr_th ur uth
     const T Fr = fma(T(0.5), fma(-K.dgrr_r, urur, Qr), fma(K.r, uthuth, -K.dgrr_th * uruth));
     // F_th = Qth/2 + dgrr_th ur^2 / 2 + a^2 s c uth^2 - 2 r ur uth
-    const T Fth = fma(T(0.5), fma(K.dgrr_th, urur, Qth), fma(K.a2sc, uthuth, T(-2) * K.r * uruth));
+    const T Fth = fma(T(0.5), fma(K.dgrr_th, urur, Qth), fma(K.a2sc, uthuth, -K.twor * uruth));
 
-    // raise: (t, phi) block inverse = (1 / (-Delta s^2)) [[g_pp, -g_tp], [-g_tp, g_tt]]
-    at = K.iDs2 * fma(K.gpp, Wt, -K.gtp * Wp);
-    aph = K.iDs2 * fma(K.gtt, Wp, -K.gtp * Wt);
+    // raise: (t, phi) block inverse = -[[Rtt, -Rtp], [-Rtp, Rpp]], F_t = -Wt, F_phi = -Wp
+    at = fma(K.Rtt, Wt, -K.Rtp * Wp);
+    aph = fma(K.Rpp, Wp, -K.Rtp * Wt);
     ar = Fr * K.Dirho2;
     ath = Fth * K.irho2;
     if (keep) *keep = KerrContr<T>{Pt_r, Pt_th, Pp_r, Pp_th, Wt, Wp, Fr, Fth};

@@ -24,18 +24,37 @@ struct Spacetime {
 // addition does not cancel).
 constexpr double kRotMax = 0.125;
 
+// a * b + c as one three-address v_fma_f64.  Used for the polynomial steps below,
+// whose addend is a loop-invariant constant: the compiler's own choice there is the
+// two-address v_fmac_f64 plus a copy of the constant into the destination.
+__device__ __forceinline__ double fma3(double a, double b, double c)
+{
+    double r;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
+// Inverse factorials used by the sin / cos polynomials (Taylor coefficients).
+constexpr double kF2 = 1.0 / 2.0, kF3 = 1.0 / 6.0, kF4 = 1.0 / 24.0, kF5 = 1.0 / 120.0,
+                 kF6 = 1.0 / 720.0, kF7 = 1.0 / 5040.0, kF8 = 1.0 / 40320.0, kF9 = 1.0 / 362880.0,
+                 kF10 = 1.0 / 3628800.0, kF11 = 1.0 / 39916800.0, kF12 = 1.0 / 479001600.0,
+                 kF13 = 1.0 / 6227020800.0, kF14 = 1.0 / 87178291200.0,
+                 kF15 = 1.0 / 1307674368000.0, kF16 = 1.0 / 20922789888000.0,
+                 kF17 = 1.0 / 355687428096000.0, kF18 = 1.0 / 6402373705728000.0;
+
 __device__ __forceinline__ void rotate(double s0, double c0, double d, double &s, double &c)
 {
     const double d2 = d * d;
-    double ps = fma(d2, 1.0 / 362880.0, -1.0 / 5040.0);
-    ps = fma(d2, ps, 1.0 / 120.0);
-    ps = fma(d2, ps, -1.0 / 6.0);
+    // sin d = d + d^3 ps(d^2),  cos d = 1 - d^2 pc(d^2)
+    double ps = fma3(d2, kF9, -kF7);
+    ps = fma3(d2, ps, kF5);
+    ps = fma3(d2, ps, -kF3);
     const double sd = fma(d * d2, ps, d);
-    double pc = fma(d2, -1.0 / 3628800.0, 1.0 / 40320.0);
-    pc = fma(d2, pc, -1.0 / 720.0);
-    pc = fma(d2, pc, 1.0 / 24.0);
-    pc = fma(d2, pc, -0.5);
-    const double cd = fma(d2, pc, 1.0);
+    double pc = fma3(d2, kF10, -kF8);
+    pc = fma3(d2, pc, kF6);
+    pc = fma3(d2, pc, -kF4);
+    pc = fma(d2, pc, kF2);
+    const double cd = fma(-d2, pc, 1.0);
     s = fma(s0, cd, c0 * sd);
     c = fma(c0, cd, -s0 * sd);
 }
@@ -53,22 +72,22 @@ __device__ __forceinline__ void sincos_0pi(double th, double &s, double &c)
     const double k = rint(th * k2OverPi);
     const double x = fma(-k, kPio2Lo, fma(-k, kPio2Hi, th));
     const double x2 = x * x;
-    double ps = fma(x2, 1.0 / 355687428096000.0, -1.0 / 1307674368000.0);  // x^17, x^15
-    ps = fma(x2, ps, 1.0 / 6227020800.0);
-    ps = fma(x2, ps, -1.0 / 39916800.0);
-    ps = fma(x2, ps, 1.0 / 362880.0);
-    ps = fma(x2, ps, -1.0 / 5040.0);
-    ps = fma(x2, ps, 1.0 / 120.0);
-    ps = fma(x2, ps, -1.0 / 6.0);
+    double ps = fma3(x2, kF17, -kF15);
+    ps = fma3(x2, ps, kF13);
+    ps = fma3(x2, ps, -kF11);
+    ps = fma3(x2, ps, kF9);
+    ps = fma3(x2, ps, -kF7);
+    ps = fma3(x2, ps, kF5);
+    ps = fma3(x2, ps, -kF3);
     const double sx = fma(x * x2, ps, x);
-    double pc = fma(x2, 1.0 / 6402373705728000.0, -1.0 / 20922789888000.0);  // x^18, x^16
-    pc = fma(x2, pc, 1.0 / 87178291200.0);
-    pc = fma(x2, pc, -1.0 / 479001600.0);
-    pc = fma(x2, pc, 1.0 / 3628800.0);
-    pc = fma(x2, pc, -1.0 / 40320.0);
-    pc = fma(x2, pc, 1.0 / 720.0);
-    pc = fma(x2, pc, -1.0 / 24.0);
-    pc = fma(x2, pc, 0.5);
+    double pc = fma3(x2, kF18, -kF16);
+    pc = fma3(x2, pc, kF14);
+    pc = fma3(x2, pc, -kF12);
+    pc = fma3(x2, pc, kF10);
+    pc = fma3(x2, pc, -kF8);
+    pc = fma3(x2, pc, kF6);
+    pc = fma3(x2, pc, -kF4);
+    pc = fma(x2, pc, kF2);
     const double cx = fma(-x2, pc, 1.0);
     // k = 0: (sx, cx); k = 1: (cx, -sx); k = 2: (-sx, -cx)
     s = k == 1.0 ? cx : (k == 0.0 ? sx : -sx);
