@@ -425,15 +425,20 @@ static int stage_in_zone(const double sr[3], double r_stop)
 }
 
 /* Fixed-step integration of one lane: up to n_steps RK4 steps while ACTIVE.
- * Returns the number of steps evaluated. */
+ * Returns the number of steps evaluated.  hamiltonian != 0: the state holds
+ * (x^mu, p_mu) and the step is the canonical one; the termination rules read r and
+ * theta from x and are the same for both formulations. */
 static int64_t integrate_lane(double M, double a, double h, int64_t n_steps, double hf, double r_esc,
-                              double y[8], int32_t *status)
+                              int hamiltonian, double y[8], int32_t *status)
 {
     double rh = hf * oracle_r_horizon(M, a);
     int64_t n;
     for (n = 0; n < n_steps && *status == ST_ACTIVE; ++n) {
         double y1[8], sr[3];
-        d_rk4_step_stages(M, a, h, y, y1, sr);
+        if (hamiltonian)
+            d_rk4_step_hamiltonian_stages(M, a, h, y, y1, sr);
+        else
+            d_rk4_step_stages(M, a, h, y, y1, sr);
         if (stage_in_zone(sr, rh)) { *status = ST_HORIZON; continue; }
         if (!usable(y1)) { *status = ST_NONFINITE; continue; }
         memcpy(y, y1, sizeof y1);
@@ -458,17 +463,8 @@ int oracle_integrate(const double *Ma, const int32_t *st_of_lane, int64_t n, dou
         double M = Ma[2 * st], a = Ma[2 * st + 1];
         double y[8];
         get_state(state, n, i, y);
-        int64_t taken;
-        if (!hamiltonian) {
-            taken = integrate_lane(M, a, h, n_steps, horizon_factor, r_escape, y, &status[i]);
-        } else {
-            /* paper formulation: state holds (x^mu, p_mu); no termination */
-            for (taken = 0; taken < n_steps; ++taken) {
-                double y1[8];
-                d_rk4_step_hamiltonian(M, a, h, y, y1);
-                memcpy(y, y1, sizeof y1);
-            }
-        }
+        int64_t taken = integrate_lane(M, a, h, n_steps, horizon_factor, r_escape, hamiltonian, y,
+                                       &status[i]);
         steps[i] += (int32_t)taken;
         put_state(state, n, i, y);
     }

@@ -149,7 +149,8 @@ def test_hamiltonian_and_christoffel_integrations_agree(orc):
     for i in range(s0.shape[1]):
         g = orc.metric(1.0, 0.9, s0[1, i], s0[2, i])
         z0[4:, i] = g @ s0[4:, i]
-    zh, _, _ = orc.integrate([(1.0, 0.9)], z0, h, n, hamiltonian=True)
+    zh, _, _ = orc.integrate([(1.0, 0.9)], z0, h, n, hamiltonian=True, r_escape=1e300,
+                             horizon_factor=0.0)
     uh = np.zeros_like(zh[4:])
     for i in range(zh.shape[1]):
         gi = orc.inverse_metric(1.0, 0.9, zh[1, i], zh[2, i])
