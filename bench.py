@@ -69,6 +69,8 @@ def parse():
                    help="oracle sample: this many strided lanes x the full step count")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-f32k", action="store_true", help="skip the FP32-compensated leg")
+    p.add_argument("--no-ham", action="store_true", help="skip the Hamiltonian-form leg")
+    p.add_argument("--no-traj", action="store_true", help="skip the trajectory-output leg")
     p.add_argument("--no-extra", action="store_true",
                    help="skip the camera, mixed-spin batch and adjoint legs")
     p.add_argument("--probe-copy-bytes", type=int, default=0,
@@ -220,6 +222,76 @@ def main():
                           "pos_err_vs_f64_p50": float(np.quantile(pos, 0.5)),
                           "pos_err_vs_f64_p99": float(np.quantile(pos, 0.99)),
                           "status_agree_frac": float(((status == st64).float().mean()).item())}
+
+    if not args.no_ham:
+        # Hamilton's equations (Section 2, eq. Ham) on the same initial data: state
+        # (x^mu, p_mu), converted once before timing
+        z0 = s0.clone()
+        m.convert_state(z0, st, True)
+        ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+
+        def run_ham(record):
+            state.copy_(z0)
+            status.zero_()
+            steps.zero_()
+            if record:
+                ev[0].record()
+            m.integrate(state, status, steps, st, h=h, n_steps=n_rk, block=args.block,
+                        formulation="hamiltonian")
+            if record:
+                ev[1].record()
+        run_ham(False)
+        torch.cuda.synchronize()
+        run_ham(True)
+        torch.cuda.synchronize()
+        dt = ev[0].elapsed_time(ev[1]) / 1e3
+        h_steps = int(steps.sum().item())
+        m.convert_state(state, st, False)
+        m.invariants(state, st, out=inv1)
+        j1 = inv1.cpu().numpy()
+        acth = (status == 0).cpu().numpy() & act
+        qh = acth & (i0[2] >= 0.1)
+        dQh = np.abs(j1[2] / i0[2] - 1)[qh]
+        vh = h_steps / dt
+        ach = m.FLOPS_PER_STEP_F64_HAM * h_steps / dt / 1e12
+        result["hamiltonian"] = {
+            "value": vh, "unit": "lane-steps/s", "speedup_vs_christoffel": vh / result["value"],
+            "kernel_ms": 1e3 * dt, "flops_per_lane_step": m.FLOPS_PER_STEP_F64_HAM,
+            "achieved_tflops": ach, "frac": ach / PEAK_FP64_VECTOR_TFLOPS,
+            "dE_over_E_max": float(np.abs(j1[0] / i0[0] - 1)[acth].max()),
+            "dQ_over_Q_p99": float(np.quantile(dQh, 0.99)),
+            "dQ_over_Q_max": float(dQh.max())}
+
+    if not args.no_traj:
+        # the paper's output stream: (tau, t, x, y, z) of every lane every 200 steps,
+        # moved to pinned host memory on a second stream while the next chunk runs
+        from paper_1803_08320_amd.stream import stream_trajectories
+        every, per_chunk = 200, 10
+        seen = {"bytes": 0}
+
+        def sink(recs, k):
+            seen["bytes"] += recs.nbytes
+            seen["tau_last"] = float(recs[-1, 0, 0])
+
+        def run_stream():
+            state.copy_(s0)
+            status.zero_()
+            steps.zero_()
+            return stream_trajectories(state, status, steps, st, h, n_rk, every, per_chunk, sink,
+                                       block=args.block)
+        run_stream()  # warm-up (allocates the pinned buffers)
+        seen["bytes"] = 0
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        info = run_stream()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        ls = int(steps.sum().item())
+        result["trajectory_stream"] = {
+            "value": ls / dt, "unit": "lane-steps/s", "vs_no_output": ls / dt / result["value"],
+            "record_every": every, "records": info["records"], "chunks": info["chunks"],
+            "bytes_to_host": seen["bytes"], "host_GB_per_s": seen["bytes"] / dt / 1e9,
+            "wall_s": dt}
 
     if not args.no_extra:
         result["extra"] = extra_legs(m, torch, np)

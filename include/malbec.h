@@ -68,6 +68,12 @@ extern "C" {
 #define MALBEC_F64 0       /* FP64 throughout */
 #define MALBEC_F32_KAHAN 1 /* FP32 state with compensated update, FP64 near the horizon */
 
+/* Formulation of the geodesic ODE (malbec_run.formulation) and with it the meaning of
+ * state components 4..7. */
+#define MALBEC_FORM_CHRISTOFFEL 0 /* y = (x^mu, u^mu), du/dtau = -Gamma u u (default) */
+#define MALBEC_FORM_HAMILTONIAN 1 /* z = (x^mu, p_mu), Hamilton's equations (Section 2,
+                                     eq. Ham); p_t = -E and p_phi = L_z stay exact */
+
 #define MALBEC_IC_CANONICAL 0 /* the paper's initial-condition rows (Section 5 table) */
 #define MALBEC_IC_CIRCULAR 1  /* equatorial near-circular orbits (Sections 3-4) */
 #define MALBEC_IC_CONSTANTS 2 /* random (E, L_z, Carter Q) with potential rejection */
@@ -134,7 +140,8 @@ typedef struct {
     int32_t checkpoint_every;/* K > 0: write the state every K steps (see malbec_integrate) */
     int32_t persistent;      /* 1: persistent kernel refilling lanes that stop early from a
                                 work counter in ws (needs persistent = 0 for checkpoints) */
-    int32_t pad_;
+    int32_t formulation;     /* MALBEC_FORM_*; HAMILTONIAN needs precision F64 and no
+                                checkpoints (MALBEC_ENOTSUP otherwise) */
 } malbec_run;
 
 /* Camera (malbec_trace_camera): Bardeen image plane of a static observer at
@@ -189,7 +196,9 @@ MALBEC_API int malbec_init_particles(const malbec_ic_spec *spec, const malbec_ba
  * the step's start state kept); the result is non-finite or has theta outside (0, pi)
  * (NONFINITE, start state kept); r <= horizon_factor r_+ (HORIZON); r >= r_escape
  * (ESCAPE).  Lanes not ACTIVE on entry are not touched.  Calling twice with n_steps/2
- * gives bitwise the same result as one call with n_steps.
+ * gives bitwise the same result as one call with n_steps.  With run->formulation =
+ * MALBEC_FORM_HAMILTONIAN the state holds (x^mu, p_mu) and the step is the RK4 step
+ * of Hamilton's equations (Section 2, eq. Ham), under the same stop rules.
  * checkpoints: device (nullable, F64 only): if run->checkpoint_every = K > 0, slot
  * s = 0 .. n_steps/K receives the state after s*K steps of this call, at
  * checkpoints[s * 8n + k * n + i]; a lane stopped earlier repeats its final state.
@@ -199,6 +208,23 @@ MALBEC_API int malbec_init_particles(const malbec_ic_spec *spec, const malbec_ba
 MALBEC_API int malbec_integrate(const malbec_run *run, const malbec_batch *b, int64_t n, double *state,
                      int32_t *status, int32_t *steps, double *checkpoints, void *ws,
                      size_t ws_bytes, void *stream);
+
+/* malbec_integrate (FP64, either formulation, one launch) that also records the
+ * paper's trajectory output (Section 5: affine parameter tau, coordinate time t and
+ * the Cartesian position of Section 2, eq. coord, x = sqrt(r^2 + a^2) sin(theta)
+ * cos(phi), y = sqrt(r^2 + a^2) sin(theta) sin(phi), z = r cos(theta)) every
+ * record_every steps.  traj: device, (n_steps / record_every) * 5 * n doubles (out);
+ * record s holds the lane after (s + 1) * record_every steps of this call at
+ * traj[(s * 5 + k) * n + i], k = (tau, t, x, y, z), tau = h * steps[i] (steps
+ * accumulated over calls, so lanes that start at tau = 0 with steps = 0 report their
+ * affine parameter).  A lane that has stopped repeats its last record.  n_steps must
+ * be a multiple of record_every; run->persistent, checkpoint_every and
+ * steps_per_chunk must be 0 (MALBEC_ENOTSUP otherwise).  The state, status and steps
+ * end exactly as malbec_integrate leaves them.
+ * Errors: MALBEC_EINVAL, MALBEC_ENOTSUP, MALBEC_EDEVICE. */
+MALBEC_API int malbec_integrate_record(const malbec_run *run, const malbec_batch *b, int64_t n,
+                                       double *state, int32_t *status, int32_t *steps,
+                                       int32_t record_every, double *traj, void *stream);
 
 /* Trace the nx * ny pixels of a camera backward until each photon stops (status
  * HORIZON, ESCAPE, DISK, NONFINITE or BUDGET), with the rules of malbec_integrate
@@ -221,6 +247,15 @@ MALBEC_API int malbec_trace_camera(const malbec_camera *cam, int32_t *status, in
  * Errors: MALBEC_EINVAL, MALBEC_EDEVICE. */
 MALBEC_API int malbec_invariants(const malbec_batch *b, int64_t n, const double *state, double *out,
                       void *stream);
+
+/* Convert n states in place between the two formulations: to_momenta = 1 lowers
+ * the index, (x, u^mu) -> (x, p_mu = g_{mu nu} u^nu); to_momenta = 0 raises it,
+ * (x, p_mu) -> (x, u^mu = g^{mu nu} p_nu), with the metric of Section 2, eq. kerr at
+ * each lane's (r, theta).  state: device 8n (in/out).  The canonical momenta are the
+ * covariant ones (p_t = -E; the paper's printed tables use +E).
+ * Errors: MALBEC_EINVAL, MALBEC_EDEVICE. */
+MALBEC_API int malbec_convert_state(const malbec_batch *b, int64_t n, double *state,
+                                    int32_t to_momenta, void *stream);
 
 /* Discrete adjoint of malbec_integrate (FP64): the exact gradient of the computed RK4
  * map.  Inputs describe a forward call made with run->checkpoint_every = K > 0 that

@@ -83,6 +83,8 @@ def lib():
         "oracle_integrate": (C.c_int, [P(d), vp, i64, P(d), P(i32), P(i32), d, i64, d, d,
                                        C.c_int, C.c_int]),
         "oracle_invariants": (C.c_int, [P(d), vp, i64, P(d), P(d)]),
+        "oracle_integrate_adaptive": (C.c_int, [P(d), vp, i64, P(d), P(d), P(d), P(i32), P(i32),
+                                                P(i32), d, d, d, d, d, d, i64, d, d, C.c_int]),
         "oracle_camera_ic": (None, [d, d, d, d, d, i64, i64, i64, i64, P(d)]),
         "oracle_trace_camera": (C.c_int, [d, d, d, d, d, i64, i64, d, d, d, d, d, d, i64, i64,
                                           P(i64), P(i32), P(i32), P(d), vp, C.c_int]),
@@ -259,6 +261,28 @@ def integrate(spacetimes, state, h, n_steps, status=None, steps=None, horizon_fa
     lib().oracle_integrate(_dp(Ma), stp, n, _dp(s), _ip(status), _ip(steps), h, n_steps,
                            horizon_factor, r_escape, int(hamiltonian), nthreads)
     return s.reshape(8, n), status, steps
+
+
+def integrate_adaptive(spacetimes, state, tau_end, h0, rtol=1e-10, atol=1e-10, fac=0.9,
+                       facmin=0.2, facmax=5.0, max_attempts=1 << 20, tau=None, h=None,
+                       status=None, steps=None, rejects=None, horizon_factor=1.01,
+                       r_escape=1500.0, st_of_lane=None, nthreads=0):
+    """Dormand-Prince 5(4) with per-lane step-size control up to tau_end (copies);
+    returns (state, tau, h, status, steps, rejects)."""
+    state = np.array(state, dtype=np.float64, copy=True)
+    n = state.shape[1]
+    s = np.ascontiguousarray(state.reshape(-1))
+    tau = np.zeros(n) if tau is None else np.array(tau, np.float64, copy=True)
+    h = np.full(n, float(h0)) if h is None else np.array(h, np.float64, copy=True)
+    status = np.zeros(n, np.int32) if status is None else np.array(status, np.int32, copy=True)
+    steps = np.zeros(n, np.int32) if steps is None else np.array(steps, np.int32, copy=True)
+    rejects = np.zeros(n, np.int32) if rejects is None else np.array(rejects, np.int32, copy=True)
+    Ma = _Ma(spacetimes)
+    _keep, stp = _st_ptr(st_of_lane, n)
+    lib().oracle_integrate_adaptive(_dp(Ma), stp, n, _dp(s), _dp(tau), _dp(h), _ip(status),
+                                    _ip(steps), _ip(rejects), tau_end, rtol, atol, fac, facmin,
+                                    facmax, max_attempts, horizon_factor, r_escape, nthreads)
+    return s.reshape(8, n), tau, h, status, steps, rejects
 
 
 def invariants(spacetimes, state, st_of_lane=None):

@@ -486,6 +486,130 @@ int oracle_invariants(const double *Ma, const int32_t *st_of_lane, int64_t n, co
 }
 
 /* ================================================================================ */
+/* Adaptive integration: Dormand-Prince 5(4) with per-lane step-size control          */
+/* ================================================================================ */
+/* The paper integrates with the fixed-step classic RK4 and announces other members
+ * of the Runge-Kutta family (Section 5).  This is the embedded pair of Dormand and
+ * Prince (J. Comput. Appl. Math. 6 (1980) 19-26): seven stages, the last evaluated
+ * at the new point (first same as last), a 5th-order solution y1 and a 4th-order
+ * companion y1*.  Step-size control (Hairer, Norsett and Wanner, Solving Ordinary
+ * Differential Equations I, Section II.4):
+ *   sc_i = atol + rtol max(|y_i|, |y1_i|),  err = sqrt(mean_i ((y1_i - y1*_i) / sc_i)^2),
+ *   accept iff err <= 1,  h_new = h min(facmax', max(facmin, fac err^(-1/5))),
+ * with facmax' = 1 for the attempt right after a rejection, facmax otherwise.  The
+ * last attempt of a call is shortened to land on tau_end.  Stop rules as for RK4
+ * (R5-R8): a stage point at r <= r_stop ends the lane as HORIZON and a non-finite
+ * or off-range result (or error) as NONFINITE, both keeping the start state;
+ * after an accepted step r <= r_stop is HORIZON and r >= r_escape ESCAPE; a lane
+ * that has used max_attempts attempts in the call without reaching tau_end ends
+ * as BUDGET.  Rejected attempts count in `rejects`, accepted ones in `steps`. */
+static const double DP_A[7][6] = {
+    {0, 0, 0, 0, 0, 0},
+    {1.0 / 5, 0, 0, 0, 0, 0},
+    {3.0 / 40, 9.0 / 40, 0, 0, 0, 0},
+    {44.0 / 45, -56.0 / 15, 32.0 / 9, 0, 0, 0},
+    {19372.0 / 6561, -25360.0 / 2187, 64448.0 / 6561, -212.0 / 729, 0, 0},
+    {9017.0 / 3168, -355.0 / 33, 46732.0 / 5247, 49.0 / 176, -5103.0 / 18656, 0},
+    {35.0 / 384, 0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84}};
+static const double DP_B[7] = {35.0 / 384, 0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84, 0};
+static const double DP_BS[7] = {5179.0 / 57600, 0, 7571.0 / 16695, 393.0 / 640,
+                                -92097.0 / 339200, 187.0 / 2100, 1.0 / 40};
+
+/* One attempt of size h from y with k[0] = f(y): fills k[1..6], y1 (5th order),
+ * e = y1 - y1* and the radii of the stage points 2..6. */
+static void dp45_attempt(double M, double a, double h, const double y[8], double k[7][8],
+                         double y1[8], double e[8], double stage_r[5])
+{
+    for (int s = 1; s < 7; ++s) {
+        double Y[8];
+        for (int c = 0; c < 8; ++c) {
+            double acc = 0.0;
+            for (int j = 0; j < s; ++j) acc += DP_A[s][j] * k[j][c];
+            Y[c] = y[c] + h * acc;
+        }
+        if (s < 6) stage_r[s - 1] = Y[1];
+        if (s == 6) memcpy(y1, Y, sizeof Y); /* the 7th row of A is the 5th-order weights */
+        d_rhs(M, a, Y, k[s]);
+    }
+    for (int c = 0; c < 8; ++c) {
+        double acc = 0.0;
+        for (int j = 0; j < 7; ++j) acc += (DP_B[j] - DP_BS[j]) * k[j][c];
+        e[c] = h * acc;
+    }
+}
+
+typedef struct {
+    double tau_end, rtol, atol, fac, facmin, facmax;
+    int64_t max_attempts;
+} dp_ctl;
+
+static void adaptive_lane(double M, double a, const dp_ctl *ctl, double r_stop, double r_esc,
+                          double y[8], double *tau, double *h, int32_t *status, int32_t *steps,
+                          int32_t *rejects)
+{
+    double k[7][8];
+    d_rhs(M, a, y, k[0]);
+    double facmax = ctl->facmax;
+    for (int64_t att = 0; *status == ST_ACTIVE && *tau < ctl->tau_end; ++att) {
+        if (att == ctl->max_attempts) { *status = ST_BUDGET; break; }
+        double hh = *h;
+        int last = 0;
+        if (*tau + hh >= ctl->tau_end) { hh = ctl->tau_end - *tau; last = 1; }
+        double y1[8], e[8], sr[5];
+        dp45_attempt(M, a, hh, y, k, y1, e, sr);
+        int in_zone = 0;
+        for (int j = 0; j < 5; ++j) in_zone |= sr[j] <= r_stop;
+        if (in_zone) { *status = ST_HORIZON; break; }
+        double sum = 0.0;
+        for (int c = 0; c < 8; ++c) {
+            double sc = ctl->atol + ctl->rtol * fmax(fabs(y[c]), fabs(y1[c]));
+            sum += (e[c] / sc) * (e[c] / sc);
+        }
+        double err = sqrt(sum / 8.0);
+        if (!usable(y1) || !isfinite(err)) { *status = ST_NONFINITE; break; }
+        double grow = err > 0.0 ? ctl->fac * pow(err, -0.2) : ctl->facmax;
+        if (err <= 1.0) {
+            memcpy(y, y1, sizeof y1);
+            memcpy(k[0], k[6], sizeof k[6]);
+            *tau = last ? ctl->tau_end : *tau + hh;
+            ++*steps;
+            *h = hh * fmin(facmax, fmax(ctl->facmin, grow));
+            facmax = ctl->facmax;
+            if (y[1] <= r_stop) *status = ST_HORIZON;
+            else if (y[1] >= r_esc) *status = ST_ESCAPE;
+        } else {
+            ++*rejects;
+            *h = hh * fmin(1.0, fmax(ctl->facmin, grow));
+            facmax = 1.0;
+        }
+    }
+}
+
+/* Batch driver (OpenMP over lanes): state, tau, h, status, steps, rejects in/out. */
+int oracle_integrate_adaptive(const double *Ma, const int32_t *st_of_lane, int64_t n, double *state,
+                              double *tau, double *h, int32_t *status, int32_t *steps,
+                              int32_t *rejects, double tau_end, double rtol, double atol,
+                              double fac, double facmin, double facmax, int64_t max_attempts,
+                              double horizon_factor, double r_escape, int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+    dp_ctl ctl = {tau_end, rtol, atol, fac, facmin, facmax, max_attempts};
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; ++i) {
+        int st = st_of_lane ? st_of_lane[i] : 0;
+        double M = Ma[2 * st], a = Ma[2 * st + 1];
+        double y[8];
+        get_state(state, n, i, y);
+        adaptive_lane(M, a, &ctl, horizon_factor * oracle_r_horizon(M, a), r_escape, y, &tau[i],
+                      &h[i], &status[i], &steps[i], &rejects[i]);
+        put_state(state, n, i, y);
+    }
+    return 0;
+}
+
+/* ================================================================================ */
 /* Camera: backward-traced null geodesics with a thin equatorial disk                */
 /* ================================================================================ */
 /* Image plane (Bardeen 1973) of a static observer at (r_obs, theta_obs = incl,

@@ -23,7 +23,7 @@ import torch  # noqa: F401  (loads the HIP runtime before libmalbec)
 __all__ = [
     "ICSpec", "Camera", "init_particles", "integrate", "invariants", "trace_camera",
     "workspace_bytes", "last_error", "version", "lib", "MalbecError", "STATUS", "adjoint",
-    "IntegrateFromParams",
+    "IntegrateFromParams", "convert_state", "integrate_record",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -31,13 +31,16 @@ LIB_PATH = os.path.join(_HERE, "libmalbec.so")
 
 STATUS = {"ACTIVE": 0, "HORIZON": 1, "ESCAPE": 2, "DISK": 3, "NONFINITE": 4, "BUDGET": 5}
 F64, F32_KAHAN = 0, 1
+FORM_CHRISTOFFEL, FORM_HAMILTONIAN = 0, 1
 IC_CANONICAL, IC_CIRCULAR, IC_CONSTANTS, IC_PARAMS = 0, 1, 2, 3
 OP_INTEGRATE, OP_CAMERA, OP_ADJOINT = 1, 2, 3
 MAX_SPACETIMES = 64
 
 # Algorithmic FP64 flops of one RK4 step of one lane as implemented (static count of
-# csrc/kerr_accel.hpp by csrc/flopcount.cpp: add/sub/mul/div 1, fma 2, sincos 2).
-FLOPS_PER_STEP_F64 = 534
+# csrc/kerr_accel.hpp and csrc/ham_accel.hpp by csrc/flopcount.cpp: add/sub/mul/div 1,
+# fma 2, sincos 2): Christoffel form, and Hamilton's equations.
+FLOPS_PER_STEP_F64 = 522
+FLOPS_PER_STEP_F64_HAM = 336
 
 
 class MalbecError(RuntimeError):
@@ -70,7 +73,8 @@ class c_run(C.Structure):
     _fields_ = [("h", C.c_double), ("n_steps", C.c_int64), ("precision", C.c_int32),
                 ("block", C.c_int32), ("horizon_factor", C.c_double), ("r_escape", C.c_double),
                 ("fp64_zone_factor", C.c_double), ("steps_per_chunk", C.c_int32),
-                ("checkpoint_every", C.c_int32), ("persistent", C.c_int32), ("pad_", C.c_int32)]
+                ("checkpoint_every", C.c_int32), ("persistent", C.c_int32),
+                ("formulation", C.c_int32)]
 
 
 class c_camera(C.Structure):
@@ -96,6 +100,11 @@ EXPORTS = {
                                       C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "malbec_invariants": (C.c_int, [C.POINTER(c_batch), C.c_int64, C.c_void_p, C.c_void_p,
                                     C.c_void_p]),
+    "malbec_integrate_record": (C.c_int, [C.POINTER(c_run), C.POINTER(c_batch), C.c_int64,
+                                          C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                          C.c_void_p, C.c_void_p]),
+    "malbec_convert_state": (C.c_int, [C.POINTER(c_batch), C.c_int64, C.c_void_p, C.c_int32,
+                                       C.c_void_p]),
     "malbec_adjoint": (C.c_int, [C.POINTER(c_run), C.POINTER(c_batch), C.c_int64, C.c_void_p,
                                  C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                  C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
@@ -223,12 +232,16 @@ def integrate(state: torch.Tensor, status: torch.Tensor, steps: torch.Tensor, sp
               precision: str = "f64", fp64_zone_factor: float = 1.2, block: int = 0,
               steps_per_chunk: int = 0, st_of_lane: Optional[torch.Tensor] = None,
               checkpoints: Optional[torch.Tensor] = None, checkpoint_every: int = 0,
-              persistent: bool = False, ws: Optional[torch.Tensor] = None):
-    """Advance state[8, n] in place (status, steps int32[n] in/out)."""
+              persistent: bool = False, ws: Optional[torch.Tensor] = None,
+              formulation: str = "christoffel"):
+    """Advance state[8, n] in place (status, steps int32[n] in/out).  formulation
+    "christoffel": state = (x^mu, u^mu); "hamiltonian": state = (x^mu, p_mu), see
+    convert_state."""
     n = state.shape[-1]
     prec = {"f64": F64, "f32k": F32_KAHAN}[precision]
+    form = {"christoffel": FORM_CHRISTOFFEL, "hamiltonian": FORM_HAMILTONIAN}[formulation]
     run = c_run(h, n_steps, prec, block, horizon_factor, r_escape, fp64_zone_factor,
-                steps_per_chunk, checkpoint_every, int(persistent), 0)
+                steps_per_chunk, checkpoint_every, int(persistent), form)
     b = _Batch(_spacetimes(spacetimes), st_of_lane, n)
     if checkpoint_every > 0:
         if checkpoints is None:
@@ -257,6 +270,40 @@ def invariants(state: torch.Tensor, spacetimes, st_of_lane: Optional[torch.Tenso
     _check(lib().malbec_invariants(C.byref(b.c), n, _ptr(state, torch.float64, 8 * n, "state"),
                                    _ptr(out, torch.float64, 4 * n, "out"), _stream()))
     return out
+
+
+def integrate_record(state: torch.Tensor, status: torch.Tensor, steps: torch.Tensor, spacetimes,
+                     h: float, n_steps: int, record_every: int, traj: Optional[torch.Tensor] = None,
+                     horizon_factor: float = 1.01, r_escape: float = 1500.0, block: int = 0,
+                     st_of_lane: Optional[torch.Tensor] = None, formulation: str = "christoffel"):
+    """integrate() that also records (tau, t, x, y, z) every record_every steps into
+    traj[n_steps // record_every, 5, n] (allocated if None); returns traj."""
+    n = state.shape[-1]
+    if record_every < 1 or n_steps % record_every:
+        raise ValueError("n_steps must be a positive multiple of record_every")
+    n_rec = n_steps // record_every
+    if traj is None:
+        traj = torch.empty((n_rec, 5, n), dtype=torch.float64, device=state.device)
+    form = {"christoffel": FORM_CHRISTOFFEL, "hamiltonian": FORM_HAMILTONIAN}[formulation]
+    run = c_run(h, n_steps, F64, block, horizon_factor, r_escape, 1.0, 0, 0, 0, form)
+    b = _Batch(_spacetimes(spacetimes), st_of_lane, n)
+    _check(lib().malbec_integrate_record(C.byref(run), C.byref(b.c), n,
+                                         _ptr(state, torch.float64, 8 * n, "state"),
+                                         _ptr(status, torch.int32, n, "status"),
+                                         _ptr(steps, torch.int32, n, "steps"), record_every,
+                                         _ptr(traj, torch.float64, n_rec * 5 * n, "traj"),
+                                         _stream()))
+    return traj
+
+
+def convert_state(state: torch.Tensor, spacetimes, to_momenta: bool,
+                  st_of_lane: Optional[torch.Tensor] = None):
+    """In place: (x, u^mu) -> (x, p_mu) if to_momenta, else (x, p_mu) -> (x, u^mu)."""
+    n = state.shape[-1]
+    b = _Batch(_spacetimes(spacetimes), st_of_lane, n)
+    _check(lib().malbec_convert_state(C.byref(b.c), n, _ptr(state, torch.float64, 8 * n, "state"),
+                                      int(bool(to_momenta)), _stream()))
+    return state
 
 
 @dataclass

@@ -62,18 +62,19 @@ __device__ __forceinline__ void vjp_accel(double M, double a, double r, double t
     B.Dirho2 = b_ar * X.Fr;
     const double bFth = b_ath * K.irho2;
     B.irho2 = b_ath * X.Fth;
-    // Fr = (Qr - dgrr_r urur)/2 + r uthuth - dgrr_th uruth
-    // Fth = (Qth + dgrr_th urur)/2 + a2sc uthuth - twor uruth
+    // Fr = Qr - dgrr_r urur + r uthuth + c1x2 uruth
+    // Fth = Qth - c1 urur + a2sc uthuth - twor uruth
     const double urur = ur * ur, uthuth = uth * uth, uruth = ur * uth;
-    const double bQr = 0.5 * bFr, bQth = 0.5 * bFth;
-    B.dgrr_r = -0.5 * bFr * urur;
-    B.dgrr_th = fma(0.5 * bFth, urur, -bFr * uruth);
+    const double bQr = bFr, bQth = bFth;
+    B.dgrr_r = -bFr * urur;
+    B.c1 = -bFth * urur;
+    B.c1x2 = bFr * uruth;
     B.r = bFr * uthuth;
     B.twor = -bFth * uruth;
     B.a2sc = bFth * uthuth;
-    const double burur = 0.5 * fma(bFth, K.dgrr_th, -bFr * K.dgrr_r);
+    const double burur = -fma(bFr, K.dgrr_r, bFth * K.c1);
     const double buthuth = fma(bFr, K.r, bFth * K.a2sc);
-    const double buruth = -fma(bFr, K.dgrr_th, bFth * K.twor);
+    const double buruth = fma(bFr, K.c1x2, -bFth * K.twor);
     double bur = fma(2.0 * ur, burur, uth * buruth);
     double buth = fma(2.0 * uth, buthuth, ur * buruth);
     // Qr = ut Pt_r + uph Pp_r, Qth = ut Pt_th + uph Pp_th
@@ -109,7 +110,8 @@ __device__ __forceinline__ void vjp_accel(double M, double a, double r, double t
 #define MALBEC_C(f) sr = fma(B.f, Kd.f.dr, sr); st = fma(B.f, Kd.f.dth, st);
     MALBEC_C(r) MALBEC_C(twor) MALBEC_C(Rtt) MALBEC_C(Rtp) MALBEC_C(Rpp) MALBEC_C(irho2)
     MALBEC_C(Dirho2) MALBEC_C(a2sc) MALBEC_C(dgtt_r) MALBEC_C(dgtt_th) MALBEC_C(dgtp_r)
-    MALBEC_C(dgtp_th) MALBEC_C(dgpp_r) MALBEC_C(dgpp_th) MALBEC_C(dgrr_r) MALBEC_C(dgrr_th)
+    MALBEC_C(dgtp_th) MALBEC_C(dgpp_r) MALBEC_C(dgpp_th) MALBEC_C(dgrr_r) MALBEC_C(c1)
+    MALBEC_C(c1x2)
 #undef MALBEC_C
     rbar = sr;
     thbar = st;
@@ -135,7 +137,7 @@ __device__ __forceinline__ void jt(const Spacetime &S, const double Y[6], const 
 // rk4_stages).
 __device__ __forceinline__ void vjp_step(const Spacetime &S, double h, const double y[8], double lam[8])
 {
-    AccelF64 f{S.M, S.a, 0.0, 0.0, 1.0};
+    AccelF64 f{S.M, S.a, {0.0, 0.0, 1.0}};
     const double hh = 0.5 * h;
     double Y1[6] = {y[1], y[2], y[4], y[5], y[6], y[7]};
     double at, ar, ath, aph;
@@ -236,8 +238,8 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjArgs A, StTable T)
         sincos(th0, &s0, &c0);
         KerrCoef<D> Kd;
         kerr_coef<D>(D(S.M), D(S.a), D(r0, 1.0, 0.0), D(s0, 0.0, c0), D(c0, 0.0, -s0), Kd);
-        // inverse (t, phi) block: g^tt = -Rtt, g^tphi = Rtp, g^phiphi = -Rpp
-        const D itt = -Kd.Rtt, itp = Kd.Rtp, ipp = -Kd.Rpp;
+        // inverse (t, phi) block: g^tt = -Rtt/2, g^tphi = Rtp/2, g^phiphi = -Rpp/2
+        const D itt = Kd.Rtt * D(-0.5), itp = Kd.Rtp * D(0.5), ipp = Kd.Rpp * D(-0.5);
         const double ut0 = A.ckpt[4 * n + i], uph0 = A.ckpt[7 * n + i];
         // lower with the block itself: G = inverse of the inverse block
         const double det = itt.v * ipp.v - itp.v * itp.v;

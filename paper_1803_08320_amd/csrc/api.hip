@@ -147,6 +147,14 @@ int malbec_integrate(const malbec_run *run, const malbec_batch *b, int64_t n, do
     if (run->persistent != 0 && run->persistent != 1) return fail(MALBEC_EINVAL, "persistent must be 0 or 1");
     if (run->persistent && run->checkpoint_every > 0)
         return fail(MALBEC_ENOTSUP, "checkpoints need persistent = 0");
+    if (run->formulation != MALBEC_FORM_CHRISTOFFEL && run->formulation != MALBEC_FORM_HAMILTONIAN)
+        return fail(MALBEC_EINVAL, "unknown formulation %d", run->formulation);
+    if (run->formulation == MALBEC_FORM_HAMILTONIAN) {
+        if (run->precision != MALBEC_F64)
+            return fail(MALBEC_ENOTSUP, "the Hamiltonian formulation is FP64 only");
+        if (run->checkpoint_every > 0)
+            return fail(MALBEC_ENOTSUP, "checkpoints need the Christoffel formulation");
+    }
     size_t need = malbec_workspace_bytes(MALBEC_OP_INTEGRATE, n, run->persistent);
     if (ws_bytes < need || (need > 0 && !ws))
         return fail(MALBEC_ENOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, need);
@@ -227,6 +235,8 @@ int malbec_adjoint(const malbec_run *run, const malbec_batch *b, int64_t n,
     if (run->n_steps < 1 || run->n_steps > INT32_MAX) return fail(MALBEC_EINVAL, "n_steps outside [1, 2^31)");
     if (run->checkpoint_every < 1) return fail(MALBEC_EINVAL, "checkpoint_every must be >= 1");
     if (run->precision != MALBEC_F64) return fail(MALBEC_ENOTSUP, "the adjoint is FP64 only");
+    if (run->formulation != MALBEC_FORM_CHRISTOFFEL)
+        return fail(MALBEC_ENOTSUP, "the adjoint differentiates the Christoffel formulation only");
     if (run->block < 0 || run->block > 1024 || (run->block % 64) != 0)
         return fail(MALBEC_EINVAL, "block must be a multiple of 64 in [64, 1024] or 0");
     size_t need = malbec_workspace_bytes(MALBEC_OP_ADJOINT, n, run->checkpoint_every);
@@ -251,6 +261,52 @@ int malbec_invariants(const malbec_batch *b, int64_t n, const double *state, dou
     if (rc) return rc;
     if (n == 0) return MALBEC_OK;
     return launch_invariants(T, b->st_of_lane, n, state, out, (hipStream_t)stream);
+}
+
+int malbec_integrate_record(const malbec_run *run, const malbec_batch *b, int64_t n, double *state,
+                            int32_t *status, int32_t *steps, int32_t record_every, double *traj,
+                            void *stream)
+{
+    clear_error();
+    if (!run) return fail(MALBEC_EINVAL, "run is NULL");
+    if (n < 0) return fail(MALBEC_EINVAL, "n = %lld < 0", (long long)n);
+    if (n > 0 && (!state || !status || !steps || !traj))
+        return fail(MALBEC_EINVAL, "state, status, steps and traj must be non-NULL");
+    if (n > ((int64_t)1 << 40)) return fail(MALBEC_EINVAL, "n too large");
+    if (!(run->h > 0.0) || !isfinite(run->h)) return fail(MALBEC_EINVAL, "h = %g must be > 0", run->h);
+    if (run->n_steps < 0 || run->n_steps > INT32_MAX)
+        return fail(MALBEC_EINVAL, "n_steps = %lld outside [0, 2^31)", (long long)run->n_steps);
+    if (record_every < 1) return fail(MALBEC_EINVAL, "record_every = %d must be >= 1", record_every);
+    if (run->n_steps % record_every != 0)
+        return fail(MALBEC_EINVAL, "n_steps must be a multiple of record_every");
+    if (!(run->r_escape > 0.0)) return fail(MALBEC_EINVAL, "r_escape must be > 0");
+    if (run->block < 0 || run->block > 1024 || (run->block % 64) != 0)
+        return fail(MALBEC_EINVAL, "block = %d must be a multiple of 64 in [64, 1024] or 0", run->block);
+    if (run->formulation != MALBEC_FORM_CHRISTOFFEL && run->formulation != MALBEC_FORM_HAMILTONIAN)
+        return fail(MALBEC_EINVAL, "unknown formulation %d", run->formulation);
+    if (run->precision != MALBEC_F64) return fail(MALBEC_ENOTSUP, "trajectory recording is FP64 only");
+    if (run->persistent || run->checkpoint_every > 0 || run->steps_per_chunk > 0)
+        return fail(MALBEC_ENOTSUP, "trajectory recording runs one launch, without checkpoints");
+    StTable T;
+    int rc = make_table(b, run->horizon_factor, 1.0, T);
+    if (rc) return rc;
+    if (n == 0 || run->n_steps == 0) return MALBEC_OK;
+    return launch_integrate_record(*run, T, b->st_of_lane, n, state, status, steps, record_every,
+                                   traj, (hipStream_t)stream);
+}
+
+int malbec_convert_state(const malbec_batch *b, int64_t n, double *state, int32_t to_momenta,
+                         void *stream)
+{
+    clear_error();
+    if (n < 0) return fail(MALBEC_EINVAL, "n < 0");
+    if (n > 0 && !state) return fail(MALBEC_EINVAL, "state must be non-NULL");
+    if (to_momenta != 0 && to_momenta != 1) return fail(MALBEC_EINVAL, "to_momenta must be 0 or 1");
+    StTable T;
+    int rc = make_table(b, 1.0, 1.0, T);
+    if (rc) return rc;
+    if (n == 0) return MALBEC_OK;
+    return launch_convert(T, b->st_of_lane, n, state, to_momenta, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -1,7 +1,8 @@
 // Static operation count of one FP64 RK4 step as implemented (host tool).
 //
-// Instantiates the same templates the kernels use (kerr_accel.hpp) with a
-// counting scalar type.  Counting rule: add, sub, mul, div = 1 flop each,
+// Instantiates the same templates the kernels use (kerr_accel.hpp for the
+// Christoffel form, ham_accel.hpp for Hamilton's equations) with a counting scalar
+// type.  Counting rule: add, sub, mul, div = 1 flop each,
 // fma = 2 flops, sincos = 2 (two results), negation = 0.  The count is
 // independent of the data (the code is straight-line), so one evaluation gives
 // the algorithmic flops per lane-step used for the roofline.  sin/cos of a stage
@@ -29,6 +30,7 @@ inline Counted recip(Counted x) { ++g_div; g_flops += 1; return Counted(1.0 / x.
 }
 
 #include <cmath>
+#include "ham_accel.hpp"
 #include "kerr_accel.hpp"
 
 struct AccelCount {
@@ -39,6 +41,18 @@ struct AccelCount {
         g_flops += 2;  // sincos
         Counted s(std::sin(th.v)), c(std::cos(th.v));
         malbec::kerr_accel<Counted>(M, a, r, s, c, ut, ur, uth, uph, at, ar, ath, aph);
+    }
+};
+
+struct HamCount {
+    Counted M, a;
+    malbec::HamConst<Counted> P;
+    void operator()(int, Counted r, Counted th, Counted pr, Counted pth, Counted &dt, Counted &dr,
+                    Counted &dth, Counted &dph, Counted &dpr, Counted &dpth) const
+    {
+        g_flops += 2;  // sincos
+        Counted s(std::sin(th.v)), c(std::cos(th.v));
+        malbec::kerr_ham<Counted>(M, a, r, s, c, pr, pth, P, dt, dr, dth, dph, dpr, dpth);
     }
 };
 
@@ -54,5 +68,19 @@ int main()
     malbec::rk4_step(f, Counted(0.02), y, y1, sr);
     std::printf("rhs_flops %ld\nrhs_div %ld\nrhs_fma %ld\nrhs_addmul %ld\nstep_flops %ld\nstep_fma %ld\nstep_addmul %ld\nstep_div %ld\n",
                 rhs, rhs_div, rhs_fma, rhs_am, g_flops, g_fma, g_addmul, g_div);
+
+    // Hamilton's equations: z = (t, r, theta, phi, p_t, p_r, p_theta, p_phi); the
+    // products a p_t, a p_phi are formed once per lane, not per step
+    Counted z[8] = {0.0, 7.0, 1.1, 0.0, -0.95, 0.1, 0.3, 3.0}, z1[8];
+    HamCount hf{Counted(1.0), Counted(0.9),
+                malbec::HamConst<Counted>{z[4], z[7], Counted(0.9 * z[4].v), Counted(0.9 * z[7].v)}};
+    Counted dt, dr, dth, dph, dpr, dpth;
+    g_flops = g_div = g_fma = g_addmul = 0;
+    hf(0, z[1], z[2], z[5], z[6], dt, dr, dth, dph, dpr, dpth);
+    long hrhs = g_flops;
+    g_flops = g_div = g_fma = g_addmul = 0;
+    malbec::rk4_ham_step(hf, Counted(0.02), z, z1, sr);
+    std::printf("ham_rhs_flops %ld\nham_step_flops %ld\nham_step_fma %ld\nham_step_addmul %ld\nham_step_div %ld\n",
+                hrhs, g_flops, g_fma, g_addmul, g_div);
     return 0;
 }

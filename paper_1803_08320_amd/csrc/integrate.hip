@@ -40,7 +40,19 @@ __device__ __forceinline__ void copy8(double dst[8], const double src[8])
     for (int c = 0; c < 8; ++c) dst[c] = src[c];
 }
 
-template <bool MULTI, bool CKPT>
+// One FP64 RK4 step of either formulation: the Christoffel form on (x, u), or
+// Hamilton's equations on (x, p) with the lane's constants p_t, p_phi in P.
+template <bool HAM>
+__device__ __forceinline__ void step_f64(const Spacetime &S, const HamConst<double> &P, double h,
+                                         const double y[8], double y1[8], double sr[3])
+{
+    if (HAM)
+        rk4_step_ham_f64(S, P, h, y, y1, sr);
+    else
+        rk4_step_f64(S, h, y, y1, sr);
+}
+
+template <bool MULTI, bool CKPT, bool HAM>
 __global__ void __launch_bounds__(256) rk4_f64_kernel(IntArgs A, StTable T)
 {
     __shared__ Spacetime lds_st[kMaxSt];
@@ -65,6 +77,7 @@ __global__ void __launch_bounds__(256) rk4_f64_kernel(IntArgs A, StTable T)
     double y[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) y[k] = A.state[k * A.n + i];
+    const HamConst<double> P = ham_const(S.a, y[4], y[7]);
     int32_t taken = 0;
     int32_t next_slot = 0;
     if (CKPT) next_slot = (A.k0 + A.ck_every - 1) / A.ck_every;  // first slot at or after k0
@@ -76,14 +89,14 @@ __global__ void __launch_bounds__(256) rk4_f64_kernel(IntArgs A, StTable T)
         while (taken < A.n_steps) {
             double sr[3];
             bool accept;
-            rk4_step_f64(S, A.h, y, y1, sr);
+            step_f64<HAM>(S, P, A.h, y, y1, sr);
             ++taken;
             st = terminate_f64(S, A.r_escape, sr, y1, accept);
             if (st != kActive || taken == A.n_steps) {
                 if (accept) copy8(y, y1);
                 break;
             }
-            rk4_step_f64(S, A.h, y1, y, sr);
+            step_f64<HAM>(S, P, A.h, y1, y, sr);
             ++taken;
             st = terminate_f64(S, A.r_escape, sr, y, accept);
             if (st != kActive) {
@@ -102,7 +115,7 @@ __global__ void __launch_bounds__(256) rk4_f64_kernel(IntArgs A, StTable T)
                 ++next_slot;
             }
             double y1[8], sr[3];
-            rk4_step_f64(S, A.h, y, y1, sr);
+            step_f64<HAM>(S, P, A.h, y, y1, sr);
             ++taken;
             bool accept;
             st = terminate_f64(S, A.r_escape, sr, y1, accept);
@@ -127,6 +140,7 @@ __global__ void __launch_bounds__(256) rk4_f64_kernel(IntArgs A, StTable T)
 
 // One lane of the batch as a work item of the persistent driver; the step is the
 // same rk4_step_f64 / terminate_f64 sequence as the one-thread-per-lane kernel.
+template <bool HAM>
 struct F64Prog {
     const IntArgs &A;
     const Spacetime *table;  // LDS copy (mixed batch) or kernel argument
@@ -135,6 +149,7 @@ struct F64Prog {
     struct Lane {
         double y[8];
         Spacetime S;
+        HamConst<double> P;
         int32_t st, taken;
     };
     __device__ __forceinline__ bool load(int64_t i, Lane &L)
@@ -152,13 +167,14 @@ struct F64Prog {
         L.S = table[sid];
 #pragma unroll
         for (int k = 0; k < 8; ++k) L.y[k] = A.state[k * A.n + i];
+        L.P = ham_const(L.S.a, L.y[4], L.y[7]);
         L.taken = 0;
         return A.n_steps > 0;
     }
     __device__ __forceinline__ bool step(Lane &L)
     {
         double y1[8], sr[3];
-        rk4_step_f64(L.S, A.h, L.y, y1, sr);
+        step_f64<HAM>(L.S, L.P, A.h, L.y, y1, sr);
         ++L.taken;
         bool accept;
         L.st = terminate_f64(L.S, A.r_escape, sr, y1, accept);
@@ -174,7 +190,7 @@ struct F64Prog {
     }
 };
 
-template <bool MULTI>
+template <bool MULTI, bool HAM>
 __global__ void __launch_bounds__(256) rk4_f64_persistent_kernel(IntArgs A, StTable T,
                                                                  unsigned long long *counter,
                                                                  int32_t chunk)
@@ -182,16 +198,31 @@ __global__ void __launch_bounds__(256) rk4_f64_persistent_kernel(IntArgs A, StTa
     __shared__ Spacetime lds_st[kMaxSt];
     for (int k = threadIdx.x; k < T.n_st; k += blockDim.x) lds_st[k] = T.st[k];
     __syncthreads();
-    F64Prog P{A, lds_st, MULTI, T.n_st};
+    F64Prog<HAM> P{A, lds_st, MULTI, T.n_st};
     persistent_loop(P, A.n, counter, chunk);
 }
 
-template <bool MULTI, bool CKPT>
+template <bool MULTI, bool CKPT, bool HAM>
 int launch_kernel(const IntArgs &A, const StTable &T, int block, hipStream_t s)
 {
-    hipLaunchKernelGGL((rk4_f64_kernel<MULTI, CKPT>), dim3(grid_for(A.n, block)), dim3(block), 0, s,
-                       A, T);
+    hipLaunchKernelGGL((rk4_f64_kernel<MULTI, CKPT, HAM>), dim3(grid_for(A.n, block)), dim3(block), 0,
+                       s, A, T);
     MALBEC_LAUNCH_CHECK("rk4_f64_kernel");
+    return MALBEC_OK;
+}
+
+template <bool MULTI, bool HAM>
+int launch_persistent(const IntArgs &A, const StTable &T, int block, int32_t sub,
+                      unsigned long long *counter, hipStream_t s)
+{
+    int grid = 0;
+    int rc = persistent_grid((const void *)rk4_f64_persistent_kernel<MULTI, HAM>, block, A.n, grid);
+    if (rc) return rc;
+    hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(1), 0, s, counter);
+    MALBEC_LAUNCH_CHECK("zero_u64_kernel");
+    hipLaunchKernelGGL((rk4_f64_persistent_kernel<MULTI, HAM>), dim3(grid), dim3(block), 0, s, A, T,
+                       counter, sub);
+    MALBEC_LAUNCH_CHECK("rk4_f64_persistent_kernel");
     return MALBEC_OK;
 }
 
@@ -204,6 +235,9 @@ int launch_integrate_f64(const malbec_run &run, const StTable &T, const int32_t 
     const int block = run.block > 0 ? run.block : 256;
     if (block > 256) return fail(MALBEC_EINVAL, "block %d exceeds the kernel's launch bound 256", block);
     const bool multi = st_of_lane != nullptr && T.n_st > 1;
+    const bool ham = run.formulation == MALBEC_FORM_HAMILTONIAN;
+    if (ham && checkpoints && run.checkpoint_every > 0)
+        return fail(MALBEC_ENOTSUP, "checkpoints need the Christoffel formulation");
     const int64_t total = run.n_steps;
     const int64_t chunk = run.steps_per_chunk > 0 ? run.steps_per_chunk : total;
     IntArgs A;
@@ -223,31 +257,26 @@ int launch_integrate_f64(const malbec_run &run, const StTable &T, const int32_t 
         A.k0 = 0;
         A.n_steps = (int32_t)total;
         const int32_t sub = run.steps_per_chunk > 0 ? run.steps_per_chunk : 64;
-        int grid = 0;
-        int rc = persistent_grid(multi ? (const void *)rk4_f64_persistent_kernel<true>
-                                       : (const void *)rk4_f64_persistent_kernel<false>,
-                                 block, n, grid);
-        if (rc) return rc;
         unsigned long long *counter = (unsigned long long *)ws;
-        hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(1), 0, s, counter);
-        MALBEC_LAUNCH_CHECK("zero_u64_kernel");
-        if (multi)
-            hipLaunchKernelGGL((rk4_f64_persistent_kernel<true>), dim3(grid), dim3(block), 0, s, A, T,
-                               counter, sub);
-        else
-            hipLaunchKernelGGL((rk4_f64_persistent_kernel<false>), dim3(grid), dim3(block), 0, s, A, T,
-                               counter, sub);
-        MALBEC_LAUNCH_CHECK("rk4_f64_persistent_kernel");
-        return MALBEC_OK;
+        if (ham)
+            return multi ? launch_persistent<true, true>(A, T, block, sub, counter, s)
+                         : launch_persistent<false, true>(A, T, block, sub, counter, s);
+        return multi ? launch_persistent<true, false>(A, T, block, sub, counter, s)
+                     : launch_persistent<false, false>(A, T, block, sub, counter, s);
     }
     for (int64_t k0 = 0; k0 < total; k0 += chunk) {
         A.k0 = (int32_t)k0;
         A.n_steps = (int32_t)((total - k0) < chunk ? (total - k0) : chunk);
         int rc;
         if (A.ckpt)
-            rc = multi ? launch_kernel<true, true>(A, T, block, s) : launch_kernel<false, true>(A, T, block, s);
+            rc = multi ? launch_kernel<true, true, false>(A, T, block, s)
+                       : launch_kernel<false, true, false>(A, T, block, s);
+        else if (ham)
+            rc = multi ? launch_kernel<true, false, true>(A, T, block, s)
+                       : launch_kernel<false, false, true>(A, T, block, s);
         else
-            rc = multi ? launch_kernel<true, false>(A, T, block, s) : launch_kernel<false, false>(A, T, block, s);
+            rc = multi ? launch_kernel<true, false, false>(A, T, block, s)
+                       : launch_kernel<false, false, false>(A, T, block, s);
         if (rc) return rc;
     }
     return MALBEC_OK;

@@ -61,6 +61,11 @@ int launch_adjoint(const malbec_run &run, const StTable &T, const int32_t *st_of
                    double *g_named, void *ws, hipStream_t s);
 int launch_invariants(const StTable &T, const int32_t *st_of_lane, int64_t n,
                       const double *state, double *out, hipStream_t s);
+int launch_convert(const StTable &T, const int32_t *st_of_lane, int64_t n, double *state,
+                   int32_t to_momenta, hipStream_t s);
+int launch_integrate_record(const malbec_run &run, const StTable &T, const int32_t *st_of_lane,
+                            int64_t n, double *state, int32_t *status, int32_t *steps,
+                            int32_t record_every, double *traj, hipStream_t s);
 
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 

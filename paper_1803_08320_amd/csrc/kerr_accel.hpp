@@ -50,62 +50,66 @@ MALBEC_HD inline float recip(float x)
 }
 
 // Position-dependent coefficients of the acceleration at (r, theta), with
-// s = sin theta, c = cos theta: the raising coefficients of the (t, phi) block
-// (Rtt = g_pp / (Delta s^2), Rtp = g_tp / (Delta s^2), Rpp = g_tt / (Delta s^2), the
-// inverse block being -[[Rtt, -Rtp], [-Rtp, Rpp]]), 1/rho^2, Delta/rho^2, the r and
-// theta partial derivatives of the metric, and a few products.
+// s = sin theta, c = cos theta.  The contraction below works with half the metric
+// partials (dg** hold (1/2) d g_**), so that its lowered acceleration needs no
+// factor 1/2; the raising coefficients of the (t, phi) block carry the matching
+// factor 2: Rtt = 2 g_pp / (Delta s^2), Rtp = 2 g_tp / (Delta s^2),
+// Rpp = 2 g_tt / (Delta s^2), the inverse block being
+// -(1/2) [[Rtt, -Rtp], [-Rtp, Rpp]].  Also 1/rho^2, Delta/rho^2, and
+// c1 = a^2 s c / Delta = -(1/2) d_theta g_rr, c1x2 = 2 c1.
 template <typename T>
 struct KerrCoef {
     T r, twor, Rtt, Rtp, Rpp, irho2, Dirho2, a2sc;
-    T dgtt_r, dgtt_th, dgtp_r, dgtp_th, dgpp_r, dgpp_th, dgrr_r, dgrr_th;
+    T dgtt_r, dgtt_th, dgtp_r, dgtp_th, dgpp_r, dgpp_th, dgrr_r, c1, c1x2;
 };
 
 template <typename T>
 MALBEC_HD inline void kerr_coef(T M, T a, T r, T s, T c, KerrCoef<T> &K)
 {
     const T a2 = a * a;
-    const T m2 = T(2) * M;
     const T s2 = s * s;
     const T sc = s * c;
     const T r2 = r * r;
     const T A = r2 + a2;                    // r^2 + a^2
     const T rho2 = fma(a2, c * c, r2);      // r^2 + a^2 cos^2
-    const T Delta = fma(-m2, r, A);         // r^2 - 2 M r + a^2
-    const T inv = recip(rho2 * Delta * s2); // 1 / (rho^2 Delta s^2)
+    const T Delta = fma(-(M + M), r, A);    // r^2 - 2 M r + a^2
+    const T Ds2 = Delta * s2;
+    const T inv = recip(rho2 * Ds2);        // 1 / (rho^2 Delta s^2)
     const T iDs2 = inv * rho2;              // 1 / (Delta s^2)
-    const T irho2 = inv * (Delta * s2);     // 1 / rho^2
+    const T irho2 = inv * Ds2;              // 1 / rho^2
     const T iDelta = iDs2 * s2;             // 1 / Delta
+    const T twor = r + r;
 
-    const T m2i = m2 * irho2;
-    const T q = m2i * r;                    // 2 M r / rho^2;  g_tt = q - 1
+    const T mi = M * irho2;
+    const T q = mi * twor;                  // 2 M r / rho^2;  g_tt = q - 1
     const T qs2 = q * s2;                   // g_tp = -a q s^2
     const T gpp_os2 = fma(a2, qs2, A);      // g_pp = (r^2 + a^2 + a^2 q s^2) s^2
 
-    // partial derivatives of q and of q s^2
-    const T dq_r = m2i * fma(T(-2), r2 * irho2, T(1));
-    const T sc2 = sc + sc;
+    // half partial derivatives of q and of q s^2
+    const T hdq_r = mi * fma(T(-2), r2 * irho2, T(1));
     const T a2sc = a2 * sc;
-    const T dq_th = (q * irho2) * (a2sc + a2sc);
-    const T dqs2_th = fma(dq_th, s2, q * sc2);
-    const T twor = r + r;
+    const T hdq_th = (q * irho2) * a2sc;
+    const T hdqs2_th = fma(hdq_th, s2, q * sc);
     const T grr = rho2 * iDelta;
+    const T iDelta2 = iDelta + iDelta;
 
     K.r = r;
     K.twor = twor;
-    K.Rtt = iDelta * gpp_os2;
-    K.Rtp = (-a * q) * iDelta;
-    K.Rpp = iDs2 * (q - T(1));
+    K.Rtt = iDelta2 * gpp_os2;
+    K.Rtp = (-a * q) * iDelta2;
+    K.Rpp = iDs2 * fma(T(2), q, T(-2));
     K.irho2 = irho2;
     K.Dirho2 = Delta * irho2;
     K.a2sc = a2sc;
-    K.dgtt_r = dq_r;
-    K.dgtt_th = dq_th;
-    K.dgtp_r = (-a * s2) * dq_r;
-    K.dgtp_th = -a * dqs2_th;
-    K.dgpp_r = fma(-a, K.dgtp_r, twor) * s2;                       // (2r + a^2 s^2 dq_r) s^2
-    K.dgpp_th = fma(-a * K.dgtp_th, s2, gpp_os2 * sc2);            // a^2 d(q s^2) s^2 + g_pp/s^2 2sc
-    K.dgrr_r = iDelta * fma(-grr, twor - m2, twor);                // (2r - g_rr (2r - 2M)) / Delta
-    K.dgrr_th = -(a2sc + a2sc) * iDelta;                           // -2 a^2 s c / Delta
+    K.dgtt_r = hdq_r;
+    K.dgtt_th = hdq_th;
+    K.dgtp_r = (-a * s2) * hdq_r;
+    K.dgtp_th = -a * hdqs2_th;
+    K.dgpp_r = fma(-a, K.dgtp_r, r) * s2;                 // (r + a^2 s^2 hdq_r) s^2
+    K.dgpp_th = fma(-a * K.dgtp_th, s2, gpp_os2 * sc);    // a^2 hd(q s^2) s^2 + g_pp/s^2 sc
+    K.dgrr_r = iDelta * fma(-grr, r - M, r);              // (r - g_rr (r - M)) / Delta
+    K.c1 = a2sc * iDelta;
+    K.c1x2 = K.c1 + K.c1;
 }
 
 // Intermediate products of the contraction (kept for the adjoint).
@@ -119,24 +123,24 @@ template <typename T>
 MALBEC_HD inline void kerr_contract(const KerrCoef<T> &K, T ut, T ur, T uth, T uph, T &at, T &ar,
                                     T &ath, T &aph, KerrContr<T> *keep = nullptr)
 {
-    // (d_l g_{t b}) u^b and (d_l g_{phi b}) u^b for l = r, theta
+    // (1/2) (d_l g_{t b}) u^b and (1/2) (d_l g_{phi b}) u^b for l = r, theta
     const T Pt_r = fma(K.dgtt_r, ut, K.dgtp_r * uph);
     const T Pt_th = fma(K.dgtt_th, ut, K.dgtp_th * uph);
     const T Pp_r = fma(K.dgtp_r, ut, K.dgpp_r * uph);
     const T Pp_th = fma(K.dgtp_th, ut, K.dgpp_th * uph);
 
-    // lowered acceleration components F_mu = g_{mu nu} du^nu/dtau
-    const T Wt = fma(ur, Pt_r, uth * Pt_th);   // F_t = -Wt
-    const T Wp = fma(ur, Pp_r, uth * Pp_th);   // F_phi = -Wp
-    const T Qr = fma(ut, Pt_r, uph * Pp_r);    // (t,phi) part of (d_r g_ab) u^a u^b
-    const T Qth = fma(ut, Pt_th, uph * Pp_th); // (t,phi) part of (d_th g_ab) u^a u^b
+    // lowered acceleration F_mu = g_{mu nu} du^nu/dtau: F_t = -2 Wt, F_phi = -2 Wp
+    const T Wt = fma(ur, Pt_r, uth * Pt_th);
+    const T Wp = fma(ur, Pp_r, uth * Pp_th);
+    const T Qr = fma(ut, Pt_r, uph * Pp_r);    // (1/2) (t,phi) part of (d_r g_ab) u^a u^b
+    const T Qth = fma(ut, Pt_th, uph * Pp_th); // (1/2) (t,phi) part of (d_th g_ab) u^a u^b
     const T urur = ur * ur, uthuth = uth * uth, uruth = ur * uth;
-    // F_r = Qr/2 + r uth^2 - dgrr_r ur^2 / 2 - dgrr_th ur uth
-    const T Fr = fma(T(0.5), fma(-K.dgrr_r, urur, Qr), fma(K.r, uthuth, -K.dgrr_th * uruth));
-    // F_th = Qth/2 + dgrr_th ur^2 / 2 + a^2 s c uth^2 - 2 r ur uth
-    const T Fth = fma(T(0.5), fma(K.dgrr_th, urur, Qth), fma(K.a2sc, uthuth, -K.twor * uruth));
+    // F_r = Qr - (1/2) d_r g_rr ur^2 + r uth^2 - d_th g_rr ur uth
+    const T Fr = fma(K.c1x2, uruth, fma(K.r, uthuth, fma(-K.dgrr_r, urur, Qr)));
+    // F_th = Qth + (1/2) d_th g_rr ur^2 + a^2 s c uth^2 - 2 r ur uth
+    const T Fth = fma(-K.twor, uruth, fma(K.a2sc, uthuth, fma(-K.c1, urur, Qth)));
 
-    // raise: (t, phi) block inverse = -[[Rtt, -Rtp], [-Rtp, Rpp]], F_t = -Wt, F_phi = -Wp
+    // raise with the (t, phi) block inverse and g^rr, g^thth
     at = fma(K.Rtt, Wt, -K.Rtp * Wp);
     aph = fma(K.Rpp, Wp, -K.Rtp * Wt);
     ar = Fr * K.Dirho2;

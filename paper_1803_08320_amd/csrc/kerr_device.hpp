@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "ham_accel.hpp"
 #include "kerr_accel.hpp"
 
 namespace malbec {
@@ -94,18 +95,15 @@ __device__ __forceinline__ void sincos_0pi(double th, double &s, double &c)
     c = k == 1.0 ? -sx : (k == 0.0 ? cx : -cx);
 }
 
-// FP64 geodesic right-hand side as a functor for rk4_stages.  Stage 0 evaluates
-// sin and cos of theta; the later stages of the same step, whose theta differs from
-// the stage-0 theta by an exactly computed small d, rotate that pair instead (the
-// library sincos if |d| > kRotMax).
-struct AccelF64 {
-    double M, a;
+// sin and cos of the theta of RK4 stage `stage`.  Stage 0 evaluates them and keeps
+// (theta, sin, cos); the later stages of the same step, whose theta differs from the
+// stage-0 theta by an exactly computed small d, rotate that pair instead (the library
+// sincos if |d| > kRotMax, or if the step brings theta close to a pole, where the
+// rotation's cancellation would cost relative accuracy in sin theta).
+struct StageTrig {
     double th0, s0, c0;
-    __device__ __forceinline__ void operator()(int stage, double r, double th, double ut, double ur,
-                                               double uth, double uph, double &at, double &ar,
-                                               double &ath, double &aph)
+    __device__ __forceinline__ void operator()(int stage, double th, double &s, double &c)
     {
-        double s, c;
         const double d = th - th0;
         if (stage == 0) {
             sincos_0pi(th, s, c);
@@ -113,12 +111,23 @@ struct AccelF64 {
             s0 = s;
             c0 = c;
         } else if (!(fabs(d) <= kRotMax && fabs(d) <= 0.5 * s0)) {
-            // large step, or a step that brings theta close to a pole, where the
-            // rotation's cancellation would cost relative accuracy in sin theta
             sincos(th, &s, &c);
         } else {
             rotate(s0, c0, d, s, c);
         }
+    }
+};
+
+// FP64 geodesic acceleration (Christoffel form) as a functor for rk4_stages.
+struct AccelF64 {
+    double M, a;
+    StageTrig trig;
+    __device__ __forceinline__ void operator()(int stage, double r, double th, double ut, double ur,
+                                               double uth, double uph, double &at, double &ar,
+                                               double &ath, double &aph)
+    {
+        double s, c;
+        trig(stage, th, s, c);
         kerr_accel<double>(M, a, r, s, c, ut, ur, uth, uph, at, ar, ath, aph);
     }
 };
@@ -126,8 +135,31 @@ struct AccelF64 {
 __device__ __forceinline__ void rk4_step_f64(const Spacetime &S, double h, const double y[8],
                                              double y1[8], double sr[3])
 {
-    AccelF64 f{S.M, S.a, 0.0, 0.0, 1.0};
+    AccelF64 f{S.M, S.a, {0.0, 0.0, 1.0}};
     rk4_step(f, h, y, y1, sr);
+}
+
+// FP64 canonical right-hand side (Hamiltonian form) as a functor for rk4_ham_step.
+struct HamF64 {
+    double M, a;
+    const HamConst<double> &P;
+    StageTrig trig;
+    __device__ __forceinline__ void operator()(int stage, double r, double th, double pr, double pth,
+                                               double &dt, double &dr, double &dth, double &dph,
+                                               double &dpr, double &dpth)
+    {
+        double s, c;
+        trig(stage, th, s, c);
+        kerr_ham<double>(M, a, r, s, c, pr, pth, P, dt, dr, dth, dph, dpr, dpth);
+    }
+};
+
+__device__ __forceinline__ void rk4_step_ham_f64(const Spacetime &S, const HamConst<double> &P,
+                                                 double h, const double z[8], double z1[8],
+                                                 double sr[3])
+{
+    HamF64 f{S.M, S.a, P, {0.0, 0.0, 1.0}};
+    rk4_ham_step(f, h, z, z1, sr);
 }
 
 // A step result is usable when all components are finite and theta stays in (0, pi).

@@ -49,7 +49,8 @@ def test_struct_layout_matches_header(m, tmp_path):
                    "#define O(T, f) printf(#T \".\" #f \" %zu\\n\", offsetof(T, f));\n"
                    "int main(void){P(malbec_spacetime)P(malbec_batch)P(malbec_ic_spec)"
                    "P(malbec_run)P(malbec_camera)O(malbec_ic_spec, rows)O(malbec_ic_spec, max_attempts)"
-                   "O(malbec_run, checkpoint_every)O(malbec_run, persistent)O(malbec_camera, max_steps)O(malbec_camera, persistent)"
+                   "O(malbec_run, checkpoint_every)O(malbec_run, persistent)O(malbec_run, formulation)"
+                   "O(malbec_camera, max_steps)O(malbec_camera, persistent)"
                    "O(malbec_batch, st_of_lane)return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
@@ -64,6 +65,7 @@ def test_struct_layout_matches_header(m, tmp_path):
     assert int(got["malbec_ic_spec.max_attempts"]) == m.c_ic_spec.max_attempts.offset
     assert int(got["malbec_run.checkpoint_every"]) == m.c_run.checkpoint_every.offset
     assert int(got["malbec_run.persistent"]) == m.c_run.persistent.offset
+    assert int(got["malbec_run.formulation"]) == m.c_run.formulation.offset
     assert int(got["malbec_camera.max_steps"]) == m.c_camera.max_steps.offset
     assert int(got["malbec_camera.persistent"]) == m.c_camera.persistent.offset
     assert int(got["malbec_batch.st_of_lane"]) == m.c_batch.st_of_lane.offset
@@ -76,7 +78,8 @@ def _batch(m, sts=((1.0, 0.9),)):
 
 def _run(m, **kw):
     d = dict(h=0.02, n_steps=10, precision=0, block=0, horizon_factor=1.01, r_escape=1500.0,
-             fp64_zone_factor=1.2, steps_per_chunk=0, checkpoint_every=0, persistent=0, pad_=0)
+             fp64_zone_factor=1.2, steps_per_chunk=0, checkpoint_every=0, persistent=0,
+             formulation=0)
     d.update(kw)
     return m.c_run(**d)
 
@@ -98,6 +101,8 @@ FAKE = C.c_void_p(0x1000)  # never dereferenced: every case below fails validati
     (dict(checkpoint_every=4), ((1.0, 0.9),), 4, -1),  # no checkpoint buffer
     (dict(persistent=2), ((1.0, 0.9),), 4, -1),
     (dict(persistent=1), ((1.0, 0.9),), 4, -2),        # persistent needs a workspace
+    (dict(formulation=2), ((1.0, 0.9),), 4, -1),
+    (dict(formulation=1, precision=1), ((1.0, 0.9),), 4, -4),  # Hamiltonian is FP64 only
 ])
 def test_integrate_argument_errors(m, kw, sts, n, expect):
     run = _run(m, **kw)
@@ -164,6 +169,12 @@ def test_init_and_camera_argument_errors(m):
     run = _run(m, checkpoint_every=4, precision=1)
     assert m.lib().malbec_adjoint(C.byref(run), C.byref(b), 4, FAKE, FAKE, FAKE, FAKE, FAKE, None,
                                   None, FAKE, 10 ** 9, None) == -4
+    run = _run(m, checkpoint_every=4, formulation=1)
+    assert m.lib().malbec_adjoint(C.byref(run), C.byref(b), 4, FAKE, FAKE, FAKE, FAKE, FAKE, None,
+                                  None, FAKE, 10 ** 9, None) == -4
+    assert m.lib().malbec_convert_state(C.byref(b), 4, FAKE, 2, None) == -1
+    assert m.lib().malbec_convert_state(C.byref(b), 4, None, 1, None) == -1
+    assert m.lib().malbec_convert_state(C.byref(b), 0, None, 1, None) == 0
     assert m.version() >= 300
 
 
@@ -176,3 +187,4 @@ def test_flop_count_constant(m, tmp_path):
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
     vals = dict(l.split() for l in out.strip().split("\n"))
     assert int(vals["step_flops"]) == m.FLOPS_PER_STEP_F64
+    assert int(vals["ham_step_flops"]) == m.FLOPS_PER_STEP_F64_HAM

@@ -1,0 +1,180 @@
+"""GPU parity of the Hamiltonian formulation (Section 2, eq. Ham: state (x^mu, p_mu))
+and of the state conversion against the oracle (canonical RK4 step of the oracle,
+its metric and inverse metric by Gauss-Jordan elimination)."""
+import math
+
+import numpy as np
+import pytest
+
+from parity import compare, mixed_rel
+
+pytestmark = pytest.mark.gpu
+
+KERR_RANGES = ((5.0, 50.0), (math.pi / 4, 3 * math.pi / 4), (0.92, 0.98), (2.5, 4.5), (0.0, 12.0))
+
+
+@pytest.fixture(scope="module")
+def m():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1803_08320_amd as m
+    m.lib()
+    return m
+
+
+def to_dev(x, dtype=None):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype).cuda()
+
+
+def lower(orc, sts, s, st_of_lane=None):
+    """(x, u) -> (x, p = g u) with the oracle's metric (Section 2, eq. kerr)."""
+    z = s.copy()
+    for i in range(s.shape[1]):
+        M, a = sts[0 if st_of_lane is None else st_of_lane[i]]
+        z[4:, i] = orc.metric(M, a, s[1, i], s[2, i]) @ s[4:, i]
+    return z
+
+
+def raise_(orc, sts, z, st_of_lane=None):
+    s = z.copy()
+    for i in range(z.shape[1]):
+        M, a = sts[0 if st_of_lane is None else st_of_lane[i]]
+        s[4:, i] = orc.inverse_metric(M, a, z[1, i], z[2, i]) @ z[4:, i]
+    return s
+
+
+def run_ham(m, sts, z0, h, n_steps, **kw):
+    import torch
+    n = z0.shape[1]
+    state = to_dev(z0, torch.float64)
+    status = torch.zeros(n, dtype=torch.int32, device="cuda")
+    steps = torch.zeros(n, dtype=torch.int32, device="cuda")
+    m.integrate(state, status, steps, sts, h=h, n_steps=n_steps, formulation="hamiltonian", **kw)
+    torch.cuda.synchronize()
+    return state.cpu().numpy(), status.cpu().numpy(), steps.cpu().numpy()
+
+
+def rerun_ham(orc, sts, h, n_steps, **kw):
+    return lambda z0: orc.integrate(sts, z0, h, n_steps, hamiltonian=True, **kw)
+
+
+def test_convert_state_matches_oracle_metric(m, orc):
+    import torch
+    sts = [(1.0, 0.0), (1.0, 0.5), (1.0, 0.998)]
+    n = 999
+    st_of_lane = (np.arange(n) % 3).astype(np.int32)
+    rc, s0, _, _ = orc.ic_constants(31, sts, n, KERR_RANGES, st_of_lane=st_of_lane)
+    x = to_dev(s0, torch.float64)
+    sol = to_dev(st_of_lane, torch.int32)
+    m.convert_state(x, sts, True, st_of_lane=sol)
+    z = x.cpu().numpy()
+    assert np.array_equal(z[:4], s0[:4])
+    assert mixed_rel(z, lower(orc, sts, s0, st_of_lane)).max() < 1e-14
+    m.convert_state(x, sts, False, st_of_lane=sol)
+    assert mixed_rel(x.cpu().numpy(), s0).max() < 1e-13
+    zr = lower(orc, sts, s0, st_of_lane)
+    y = to_dev(zr, torch.float64)
+    m.convert_state(y, sts, False, st_of_lane=sol)
+    assert mixed_rel(y.cpu().numpy(), raise_(orc, sts, zr, st_of_lane)).max() < 1e-14
+
+
+@pytest.mark.parametrize("a,n", [(0.9, 1000), (0.0, 300), (0.998, 257)])
+def test_hamiltonian_parity_ragged(m, orc, a, n):
+    """Several 256-lane blocks and a ragged tail, 3,000 steps of h = 0.02."""
+    st = [(1.0, a)]
+    rc, s0, _, _ = orc.ic_constants(32, st, n, KERR_RANGES)
+    z0 = lower(orc, st, s0)
+    got = run_ham(m, st, z0, 0.02, 3000)
+    ref = orc.integrate(st, z0, 0.02, 3000, hamiltonian=True)
+    compare(orc, st, z0, *got, *ref, rerun_ham(orc, st, 0.02, 3000))
+    # p_t and p_phi are constants of the canonical RK4 map, bit for bit
+    assert np.array_equal(got[0][4], z0[4]) and np.array_equal(got[0][7], z0[7])
+
+
+def test_hamiltonian_worked_example_on_gpu(m, orc):
+    """Section 5's worked example (Schwarzschild, h = 0.1) in the paper's own
+    formulation, against every printed digit."""
+    from conftest import load_golden
+    from test_oracle_integration import cartesian, paper_rows
+    gold = load_golden("worked_example.txt")
+    rows = paper_rows([6.0, 3.5])
+    for particle, tau, t, x, y, z in gold:
+        n = int(round(tau / 0.1))
+        p = int(particle)
+        z0 = rows[p].copy()
+        z0[4] = -z0[4]  # paper p_t = +E -> covariant p_t = -E
+        s, st_, sp = run_ham(m, [(1.0, 0.0)], z0.reshape(8, 1), 0.1, n)
+        X, Y, Z = cartesian(0.0, s[1, 0], s[2, 0], s[3, 0])
+        assert st_[0] == 0 and sp[0] == n
+        assert abs(s[0, 0] - t) <= 5.01e-5
+        assert abs(X - x) <= 5.01e-5 and abs(Y - y) <= 5.01e-5 and abs(Z - z) <= 5.01e-5
+
+
+def test_hamiltonian_plunging_termination_parity(m, orc):
+    st = [(1.0, 0.0)]
+    rc, s0, _, _ = orc.ic_constants(33, st, 2000, KERR_RANGES)
+    z0 = lower(orc, st, s0)
+    got = run_ham(m, st, z0, 0.02, 4000)
+    ref = orc.integrate(st, z0, 0.02, 4000, hamiltonian=True)
+    assert (ref[1] == 1).sum() > 100
+    compare(orc, st, z0, *got, *ref, rerun_ham(orc, st, 0.02, 4000))
+
+
+def test_hamiltonian_persistent_and_chunked_are_bitwise(m, orc):
+    import torch
+    sts = [(1.0, 0.99 * k / 15) for k in range(16)]
+    per = 100
+    n = 16 * per + 3
+    st_of_lane = np.concatenate([np.repeat(np.arange(16), per), np.arange(3)]).astype(np.int32)
+    rc, s0, _, _ = orc.ic_constants(34, sts, n, KERR_RANGES, st_of_lane=st_of_lane)
+    z0 = lower(orc, sts, s0, st_of_lane)
+    sol = to_dev(st_of_lane, torch.int32)
+    plain = run_ham(m, sts, z0, 0.02, 2500, st_of_lane=sol)
+    pers = run_ham(m, sts, z0, 0.02, 2500, st_of_lane=sol, persistent=True, steps_per_chunk=16)
+    chunk = run_ham(m, sts, z0, 0.02, 2500, st_of_lane=sol, steps_per_chunk=333)
+    assert (plain[1] == 1).sum() > 50
+    for x, y, w in zip(plain, pers, chunk):
+        assert np.array_equal(x, y) and np.array_equal(x, w)
+    # parity per spacetime of the mixed batch
+    for k in range(16):
+        sel = np.flatnonzero(st_of_lane == k)
+        stk = [sts[k]]
+        ref = orc.integrate(stk, z0[:, sel], 0.02, 2500, hamiltonian=True)
+        compare(orc, stk, z0[:, sel], plain[0][:, sel], plain[1][sel], plain[2][sel], *ref,
+                rerun_ham(orc, stk, 0.02, 2500))
+
+
+def test_hamiltonian_full_size_sampled(m, orc):
+    """Kerr a = 0.9, 1,048,576 lanes x 20,000 steps (the benchmark's workload in the
+    canonical variables), compared on 256 strided lanes with the oracle; over all
+    lanes E = -p_t and L_z = p_phi are exact and the Hamiltonian stays on shell."""
+    import torch
+    st = [(1.0, 0.9)]
+    n, n_steps = 1 << 20, 20000
+    spec = m.ICSpec(mode=m.IC_CONSTANTS, seed=2, r_range=KERR_RANGES[0], th_range=KERR_RANGES[1],
+                    E_range=KERR_RANGES[2], Lz_range=KERR_RANGES[3], Q_range=KERR_RANGES[4])
+    state, consts, _ = m.init_particles(spec, st, n)
+    m.convert_state(state, st, True)
+    z_dev0 = state.clone()
+    status, steps = m.new_lane_arrays(n)
+    m.integrate(state, status, steps, st, h=0.02, n_steps=n_steps, formulation="hamiltonian")
+    torch.cuda.synchronize()
+    idx = np.arange(0, n, n // 256)
+    s0 = np.concatenate([orc.ic_constants(2, st, 1, KERR_RANGES, lane0=int(i))[1] for i in idx], axis=1)
+    z0 = lower(orc, st, s0)
+    assert mixed_rel(z_dev0.cpu().numpy()[:, idx], z0).max() < 5e-13
+    ref = orc.integrate(st, z0, 0.02, n_steps, hamiltonian=True)
+    got = (state.cpu().numpy()[:, idx], status.cpu().numpy()[idx], steps.cpu().numpy()[idx])
+    compare(orc, st, z0, *got, *ref, rerun_ham(orc, st, 0.02, n_steps))
+    z = state.cpu().numpy()
+    c = consts.cpu().numpy()
+    act = status.cpu().numpy() == 0
+    assert act.mean() > 0.99
+    assert np.array_equal(z[4], z_dev0[4].cpu().numpy())
+    assert np.array_equal(z[7], z_dev0[7].cpu().numpy())
+    m.convert_state(state, st, False)
+    inv = m.invariants(state, st).cpu().numpy()
+    assert np.abs(inv[0][act] / c[0][act] - 1).max() < 1e-13
+    assert np.abs(inv[3][act] + 1).max() < 1e-8

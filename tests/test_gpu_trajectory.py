@@ -1,0 +1,155 @@
+"""The trajectory output (tau, t, x, y, z every record_every steps; Section 5's output,
+Section 2 eq. coord for the Cartesian position) against the paper's worked example
+and the oracle, and the streaming driver against the direct call."""
+import math
+
+import numpy as np
+import pytest
+
+from parity import compare, mixed_rel
+
+pytestmark = pytest.mark.gpu
+
+KERR_RANGES = ((5.0, 50.0), (math.pi / 4, 3 * math.pi / 4), (0.92, 0.98), (2.5, 4.5), (0.0, 12.0))
+
+
+@pytest.fixture(scope="module")
+def m():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1803_08320_amd as m
+    m.lib()
+    return m
+
+
+def to_dev(x, dtype=None):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype).cuda()
+
+
+def cart(a, y):
+    """Section 2, eq. coord."""
+    rr = np.sqrt(y[1] ** 2 + a * a)
+    return np.stack([rr * np.sin(y[2]) * np.cos(y[3]), rr * np.sin(y[2]) * np.sin(y[3]),
+                     y[1] * np.cos(y[2])])
+
+
+def oracle_records(orc, st, s0, h, n_steps, every, hamiltonian=False):
+    a = st[0][1]
+    y, status, steps = s0.copy(), None, None
+    recs = []
+    for _ in range(n_steps // every):
+        y, status, steps = orc.integrate(st, y, h, every, status=status, steps=steps,
+                                         hamiltonian=hamiltonian)
+        recs.append(np.concatenate([h * steps[None, :].astype(np.float64), y[0:1], cart(a, y)]))
+    return np.stack(recs), (y, status, steps)
+
+
+def gpu_records(m, st, s0, h, n_steps, every, **kw):
+    import torch
+    n = s0.shape[1]
+    state = to_dev(s0, torch.float64)
+    status = torch.zeros(n, dtype=torch.int32, device="cuda")
+    steps = torch.zeros(n, dtype=torch.int32, device="cuda")
+    traj = m.integrate_record(state, status, steps, st, h, n_steps, every, **kw)
+    torch.cuda.synchronize()
+    return traj.cpu().numpy(), (state.cpu().numpy(), status.cpu().numpy(), steps.cpu().numpy())
+
+
+@pytest.mark.parametrize("hamiltonian", [False, True])
+def test_worked_example_output_rows(m, orc, hamiltonian):
+    """The paper's printed output rows (particle, tau, t, x, y, z), Schwarzschild,
+    h = 0.1, recorded at every step by the kernel."""
+    from conftest import load_golden
+    from test_oracle_integration import paper_rows
+    gold = load_golden("worked_example.txt")
+    rows = paper_rows([6.0, 3.5])
+    for p in sorted(set(int(g[0]) for g in gold)):
+        mine = [g for g in gold if int(g[0]) == p]
+        n_max = max(int(round(g[1] / 0.1)) for g in mine)
+        if hamiltonian:
+            z0 = rows[p].copy()
+            z0[4] = -z0[4]  # paper p_t = +E -> covariant p_t = -E
+            y0 = z0.reshape(8, 1)
+        else:
+            y0 = orc.ic_canonical(1.0, 0.0, rows[p:p + 1])
+        traj, _ = gpu_records(m, [(1.0, 0.0)], y0, 0.1, n_max, 1,
+                              formulation="hamiltonian" if hamiltonian else "christoffel")
+        for _, tau, t, x, y, z in mine:
+            k = int(round(tau / 0.1)) - 1
+            if k < 0:
+                continue  # the tau = 0 row is the initial condition itself
+            rec = traj[k, :, 0]
+            assert abs(rec[0] - tau) <= 1e-12
+            assert abs(rec[1] - t) <= 5.01e-5
+            assert abs(rec[2] - x) <= 5.01e-5 and abs(rec[3] - y) <= 5.01e-5
+            assert abs(rec[4] - z) <= 5.01e-5
+
+
+@pytest.mark.parametrize("st", [[(1.0, 0.9)], [(1.0, 0.0)]])
+def test_records_match_oracle(m, orc, st):
+    """600 lanes (two blocks and a ragged tail), 2,000 steps, a record every 100: the
+    records match the oracle's states converted by eq. coord; stopped lanes repeat
+    their last record."""
+    rc, s0, _, _ = orc.ic_constants(41, st, 600, KERR_RANGES)
+    traj, got = gpu_records(m, st, s0, 0.02, 2000, 100)
+    ref_traj, ref = oracle_records(orc, st, s0, 0.02, 2000, 100)
+    compare(orc, st, s0, *got, *ref, lambda p0: orc.integrate(st, p0, 0.02, 2000))
+    good = (mixed_rel(got[0], ref[0]) <= 1e-10) & (got[1] == ref[1]) & (got[2] == ref[2])
+    assert good.mean() > 0.98
+    err = np.abs(traj - ref_traj) / (np.abs(ref_traj) + 1.0)
+    assert err[:, :, good].max() <= 1e-10
+    stopped = np.flatnonzero(got[1] != 0)
+    if st[0][1] == 0.0:
+        assert stopped.size > 10
+    for i in stopped:
+        last = int(np.ceil(got[2][i] / 100.0)) - 1
+        assert np.array_equal(traj[last:, :, i], np.repeat(traj[last:last + 1, :, i], 20 - last, 0))
+
+
+@pytest.mark.parametrize("formulation", ["christoffel", "hamiltonian"])
+def test_recording_leaves_the_integration_unchanged(m, orc, formulation):
+    import torch
+    st = [(1.0, 0.7)]
+    rc, s0, _, _ = orc.ic_constants(42, st, 777, KERR_RANGES)
+    if formulation == "hamiltonian":
+        x = to_dev(s0, torch.float64)
+        m.convert_state(x, st, True)
+        s0 = x.cpu().numpy()
+    _, a = gpu_records(m, st, s0, 0.02, 1500, 50, formulation=formulation)
+    state = to_dev(s0, torch.float64)
+    status, steps = m.new_lane_arrays(777)
+    m.integrate(state, status, steps, st, h=0.02, n_steps=1500, formulation=formulation)
+    torch.cuda.synchronize()
+    for x, y in zip(a, (state.cpu().numpy(), status.cpu().numpy(), steps.cpu().numpy())):
+        assert np.array_equal(x, y)
+
+
+def test_streaming_driver_is_the_direct_call(m, orc, tmp_path):
+    """Double-buffered chunks (7 records per chunk, a ragged last chunk) moved off the
+    device on a second stream give the same bytes as one direct call, in order, and
+    the file sink stores them as [records, 5, n]."""
+    import torch
+    from paper_1803_08320_amd.stream import FileSink, stream_trajectories
+    st = [(1.0, 0.5)]
+    n = 3000
+    rc, s0, _, _ = orc.ic_constants(43, st, n, KERR_RANGES)
+    direct, fin = gpu_records(m, st, s0, 0.02, 1000, 10)
+    state = to_dev(s0, torch.float64)
+    status, steps = m.new_lane_arrays(n)
+    got = []
+    info = stream_trajectories(state, status, steps, st, 0.02, 1000, 10, 7,
+                               lambda recs, k: got.append((k, recs.copy())))
+    assert info["chunks"] == 15 and info["records"] == 100
+    assert [k for k, _ in got] == list(range(15))
+    assert np.array_equal(np.concatenate([r for _, r in got]), direct)
+    for x, y in zip(fin, (state.cpu().numpy(), status.cpu().numpy(), steps.cpu().numpy())):
+        assert np.array_equal(x, y)
+    path = str(tmp_path / "traj.bin")
+    sink = FileSink(path)
+    state = to_dev(s0, torch.float64)
+    status, steps = m.new_lane_arrays(n)
+    stream_trajectories(state, status, steps, st, 0.02, 1000, 10, 32, sink)
+    sink.close()
+    assert np.array_equal(np.fromfile(path, dtype=np.float64).reshape(100, 5, n), direct)

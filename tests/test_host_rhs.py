@@ -1,0 +1,128 @@
+"""The kernels' right-hand sides and RK4 steps, compiled for the host with g++ from
+the same headers the GPU kernels include (csrc/kerr_accel.hpp, csrc/ham_accel.hpp),
+against the oracle: a CPU check of the kernels' algebra (the GPU tests check the
+compiled kernels themselves)."""
+import ctypes as C
+import math
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+from conftest import ROOT
+
+KERR_RANGES = ((5.0, 50.0), (math.pi / 4, 3 * math.pi / 4), (0.92, 0.98), (2.5, 4.5), (0.0, 12.0))
+
+SRC = r"""
+#include <cmath>
+#include "ham_accel.hpp"
+#include "kerr_accel.hpp"
+struct Chr {
+    double M, a;
+    void operator()(int, double r, double th, double ut, double ur, double uth, double uph,
+                    double &at, double &ar, double &ath, double &aph) const {
+        malbec::kerr_accel<double>(M, a, r, std::sin(th), std::cos(th), ut, ur, uth, uph,
+                                   at, ar, ath, aph);
+    }
+};
+struct Ham {
+    double M, a;
+    malbec::HamConst<double> P;
+    void operator()(int, double r, double th, double pr, double pth, double &dt, double &dr,
+                    double &dth, double &dph, double &dpr, double &dpth) const {
+        malbec::kerr_ham<double>(M, a, r, std::sin(th), std::cos(th), pr, pth, P, dt, dr, dth,
+                                 dph, dpr, dpth);
+    }
+};
+extern "C" void chr_rhs(double M, double a, const double *y, double *f) {
+    f[0] = y[4]; f[1] = y[5]; f[2] = y[6]; f[3] = y[7];
+    Chr{M, a}(0, y[1], y[2], y[4], y[5], y[6], y[7], f[4], f[5], f[6], f[7]);
+}
+extern "C" void ham_rhs(double M, double a, const double *z, double *f) {
+    Ham h{M, a, malbec::ham_const(a, z[4], z[7])};
+    h(0, z[1], z[2], z[5], z[6], f[0], f[1], f[2], f[3], f[5], f[6]);
+    f[4] = 0.0; f[7] = 0.0;
+}
+extern "C" void chr_step(double M, double a, double h, const double *y, double *y1) {
+    Chr f{M, a};
+    double sr[3];
+    malbec::rk4_step(f, h, y, y1, sr);
+}
+extern "C" void ham_step(double M, double a, double h, const double *z, double *z1) {
+    Ham f{M, a, malbec::ham_const(a, z[4], z[7])};
+    double sr[3];
+    malbec::rk4_ham_step(f, h, z, z1, sr);
+}
+"""
+
+
+@pytest.fixture(scope="module")
+def host(tmp_path_factory):
+    d = tmp_path_factory.mktemp("hostrhs")
+    src = d / "host_rhs.cpp"
+    src.write_text(SRC)
+    so = d / "libhost_rhs.so"
+    subprocess.run(["g++", "-O1", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
+                    "-I", os.path.join(ROOT, "paper_1803_08320_amd", "csrc"), str(src), "-o",
+                    str(so)], check=True)
+    lib = C.CDLL(str(so))
+    dp = C.POINTER(C.c_double)
+    for name in ("chr_rhs", "ham_rhs"):
+        getattr(lib, name).argtypes = [C.c_double, C.c_double, dp, dp]
+    for name in ("chr_step", "ham_step"):
+        getattr(lib, name).argtypes = [C.c_double, C.c_double, C.c_double, dp, dp]
+    return lib
+
+
+def _p(x):
+    return x.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def sample_states(orc, a, n, seed):
+    """Bound-orbit states of the Kerr draws, with r pulled towards the hole."""
+    rc, s0, _, _ = orc.ic_constants(seed, [(1.0, a)], n, KERR_RANGES)
+    rng = np.random.default_rng(seed)
+    rp = 1.0 + math.sqrt(1.0 - a * a)
+    s0[1] = 1.2 * rp + (s0[1] - 1.2 * rp) * rng.uniform(0.02, 1.0, n)
+    return s0
+
+
+def lower(orc, a, y):
+    z = y.copy()
+    z[4:] = orc.metric(1.0, a, y[1], y[2]) @ y[4:]
+    return z
+
+
+@pytest.mark.parametrize("a", [0.0, 0.5, 0.9, 0.998])
+def test_right_hand_sides_match_oracle(orc, host, a):
+    s0 = sample_states(orc, a, 200, 51)
+    for i in range(s0.shape[1]):
+        y = np.ascontiguousarray(s0[:, i])
+        f = np.zeros(8)
+        host.chr_rhs(1.0, a, _p(y), _p(f))
+        ref = orc.rhs(1.0, a, y)
+        assert np.max(np.abs(f - ref)) <= 1e-13 * np.max(np.abs(ref))
+        z = lower(orc, a, y)
+        fh = np.zeros(8)
+        host.ham_rhs(1.0, a, _p(z), _p(fh))
+        refh = orc.rhs_hamiltonian(1.0, a, z)
+        assert np.max(np.abs(fh - refh)) <= 1e-13 * np.max(np.abs(refh))
+        assert fh[4] == 0.0 and fh[7] == 0.0
+
+
+@pytest.mark.parametrize("a", [0.0, 0.9])
+def test_rk4_steps_match_oracle(orc, host, a):
+    s0 = sample_states(orc, a, 64, 52)
+    ref, _, _ = orc.integrate([(1.0, a)], s0, 0.02, 1, r_escape=1e300, horizon_factor=0.0)
+    z0 = np.stack([lower(orc, a, s0[:, i]) for i in range(s0.shape[1])], axis=1)
+    refh, _, _ = orc.integrate([(1.0, a)], z0, 0.02, 1, hamiltonian=True, r_escape=1e300,
+                               horizon_factor=0.0)
+    for i in range(s0.shape[1]):
+        y1 = np.zeros(8)
+        host.chr_step(1.0, a, 0.02, _p(np.ascontiguousarray(s0[:, i])), _p(y1))
+        assert np.max(np.abs(y1 - ref[:, i]) / (np.abs(ref[:, i]) + 1.0)) <= 1e-14
+        z1 = np.zeros(8)
+        host.ham_step(1.0, a, 0.02, _p(np.ascontiguousarray(z0[:, i])), _p(z1))
+        assert np.max(np.abs(z1 - refh[:, i]) / (np.abs(refh[:, i]) + 1.0)) <= 1e-14
+        assert z1[4] == z0[4, i] and z1[7] == z0[7, i]
