@@ -85,6 +85,7 @@ extern "C" {
 #define MALBEC_OP_INTEGRATE 1
 #define MALBEC_OP_CAMERA 2
 #define MALBEC_OP_ADJOINT 3
+#define MALBEC_OP_ADAPTIVE 4
 
 /* One Kerr spacetime: mass M > 0 and spin a in [0, M] (Section 2; a > M is a naked
  * singularity and is rejected). */
@@ -144,6 +145,22 @@ typedef struct {
                                 checkpoints (MALBEC_ENOTSUP otherwise) */
 } malbec_run;
 
+/* Adaptive integration controls (malbec_integrate_adaptive): Dormand-Prince 5(4)
+ * with the standard step-size controller. */
+typedef struct {
+    double tau_end;        /* each lane integrates until its tau reaches tau_end */
+    double rtol, atol;     /* weights sc_i = atol + rtol max(|y_i|, |y1_i|), > 0 */
+    double fac;            /* safety factor, in (0, 1] (0.9 typical) */
+    double facmin, facmax; /* bounds of h_new / h, 0 < facmin <= 1 <= facmax */
+    int64_t max_attempts;  /* attempts per lane per call, >= 1; BUDGET when used up */
+    double horizon_factor; /* stop at r <= horizon_factor * r_+ ; >= 1 */
+    double r_escape;       /* stop at r >= r_escape */
+    int32_t block;         /* threads per block, 0 = default */
+    int32_t persistent;    /* 1: work-queue kernel (lanes need different attempt counts) */
+    int32_t steps_per_chunk; /* persistent: attempts between retire/refill checks, 0 = 8 */
+    int32_t pad_;
+} malbec_adaptive;
+
 /* Camera (malbec_trace_camera): Bardeen image plane of a static observer at
  * (r_obs, theta = incl, phi = 0); pixel p = j * nx + i, alpha = -w + (i + 1/2) 2w / nx,
  * beta = -w + (j + 1/2) 2w / ny.  Photon: E = 1, L_z = -alpha sin(incl),
@@ -173,8 +190,9 @@ MALBEC_API const char *malbec_last_error(void);
 MALBEC_API int malbec_version(void);
 
 /* Bytes of caller workspace an operation needs: op = MALBEC_OP_INTEGRATE (n lanes,
- * aux = run->persistent), MALBEC_OP_CAMERA (n = nx * ny pixels) or MALBEC_OP_ADJOINT
- * (n lanes, aux = the checkpoint interval K: K * 8 * n doubles).  Returns 0 for
+ * aux = run->persistent), MALBEC_OP_CAMERA (n = nx * ny pixels), MALBEC_OP_ADJOINT
+ * (n lanes, aux = the checkpoint interval K: K * 8 * n doubles) or
+ * MALBEC_OP_ADAPTIVE (n lanes, aux = ad->persistent).  Returns 0 for
  * operations that need none. */
 MALBEC_API size_t malbec_workspace_bytes(int32_t op, int64_t n, int32_t aux);
 
@@ -247,6 +265,28 @@ MALBEC_API int malbec_trace_camera(const malbec_camera *cam, int32_t *status, in
  * Errors: MALBEC_EINVAL, MALBEC_EDEVICE. */
 MALBEC_API int malbec_invariants(const malbec_batch *b, int64_t n, const double *state, double *out,
                       void *stream);
+
+/* Adaptive FP64 integration (Christoffel form) of every ACTIVE lane with tau < tau_end
+ * by the embedded Runge-Kutta pair of Dormand and Prince, 5(4) (the paper's Section 5
+ * integrates with classic RK4 and announces other members of the family).  An attempt
+ * of size h from y gives y1 (5th order) and the difference e to the 4th-order
+ * companion; err = sqrt(mean_i (e_i / (atol + rtol max(|y_i|, |y1_i|)))^2); the attempt
+ * is accepted iff err <= 1; the next size is h min(F, max(facmin, fac err^(-1/5))),
+ * F = 1 right after a rejection and facmax otherwise; an attempt that would pass
+ * tau_end is shortened to end on it.  Stops: a stage point at r <= horizon_factor r_+
+ * (HORIZON) or a non-finite / off-range (theta outside (0, pi)) result or error
+ * (NONFINITE) end the lane with the start state kept; an accepted step reaching
+ * r <= horizon_factor r_+ (HORIZON) or r >= r_escape (ESCAPE); max_attempts attempts
+ * in this call without reaching tau_end (BUDGET).
+ * state: device 8n (in/out); tau, h: device n doubles (in/out: affine parameter and
+ * the next step size); status: device n (in/out); steps, rejects: device n int32
+ * (accumulate accepted and rejected attempts).  ws: caller workspace of
+ * malbec_workspace_bytes(MALBEC_OP_ADAPTIVE, n, ad->persistent) bytes.
+ * Errors: MALBEC_EINVAL, MALBEC_ENOMEM, MALBEC_EDEVICE. */
+MALBEC_API int malbec_integrate_adaptive(const malbec_adaptive *ad, const malbec_batch *b,
+                                         int64_t n, double *state, double *tau, double *h,
+                                         int32_t *status, int32_t *steps, int32_t *rejects,
+                                         void *ws, size_t ws_bytes, void *stream);
 
 /* Convert n states in place between the two formulations: to_momenta = 1 lowers
  * the index, (x, u^mu) -> (x, p_mu = g_{mu nu} u^nu); to_momenta = 0 raises it,

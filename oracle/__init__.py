@@ -83,6 +83,7 @@ def lib():
         "oracle_integrate": (C.c_int, [P(d), vp, i64, P(d), P(i32), P(i32), d, i64, d, d,
                                        C.c_int, C.c_int]),
         "oracle_invariants": (C.c_int, [P(d), vp, i64, P(d), P(d)]),
+        "oracle_dp45_attempt": (None, [d, d, d, P(d), P(d), P(d)]),
         "oracle_integrate_adaptive": (C.c_int, [P(d), vp, i64, P(d), P(d), P(d), P(i32), P(i32),
                                                 P(i32), d, d, d, d, d, d, i64, d, d, C.c_int]),
         "oracle_camera_ic": (None, [d, d, d, d, d, i64, i64, i64, i64, P(d)]),
@@ -261,6 +262,14 @@ def integrate(spacetimes, state, h, n_steps, status=None, steps=None, horizon_fa
     lib().oracle_integrate(_dp(Ma), stp, n, _dp(s), _ip(status), _ip(steps), h, n_steps,
                            horizon_factor, r_escape, int(hamiltonian), nthreads)
     return s.reshape(8, n), status, steps
+
+
+def dp45_attempt(M, a, h, y):
+    """One Dormand-Prince attempt: (y1 of 5th order, y1 - y1* of the 4th-order pair)."""
+    y = _f64(y)
+    y1, e = np.zeros(8), np.zeros(8)
+    lib().oracle_dp45_attempt(M, a, h, _dp(y), _dp(y1), _dp(e))
+    return y1, e
 
 
 def integrate_adaptive(spacetimes, state, tau_end, h0, rtol=1e-10, atol=1e-10, fac=0.9,

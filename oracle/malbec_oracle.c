@@ -538,6 +538,14 @@ static void dp45_attempt(double M, double a, double h, const double y[8], double
     }
 }
 
+/* One attempt from y (test hook): y1 (5th order) and e = y1 - y1* (4th order). */
+void oracle_dp45_attempt(double M, double a, double h, const double *y, double *y1, double *e)
+{
+    double k[7][8], sr[5];
+    d_rhs(M, a, y, k[0]);
+    dp45_attempt(M, a, h, y, k, y1, e, sr);
+}
+
 typedef struct {
     double tau_end, rtol, atol, fac, facmin, facmax;
     int64_t max_attempts;

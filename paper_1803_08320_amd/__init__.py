@@ -23,7 +23,7 @@ import torch  # noqa: F401  (loads the HIP runtime before libmalbec)
 __all__ = [
     "ICSpec", "Camera", "init_particles", "integrate", "invariants", "trace_camera",
     "workspace_bytes", "last_error", "version", "lib", "MalbecError", "STATUS", "adjoint",
-    "IntegrateFromParams", "convert_state", "integrate_record",
+    "IntegrateFromParams", "convert_state", "integrate_record", "integrate_adaptive",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -33,7 +33,7 @@ STATUS = {"ACTIVE": 0, "HORIZON": 1, "ESCAPE": 2, "DISK": 3, "NONFINITE": 4, "BU
 F64, F32_KAHAN = 0, 1
 FORM_CHRISTOFFEL, FORM_HAMILTONIAN = 0, 1
 IC_CANONICAL, IC_CIRCULAR, IC_CONSTANTS, IC_PARAMS = 0, 1, 2, 3
-OP_INTEGRATE, OP_CAMERA, OP_ADJOINT = 1, 2, 3
+OP_INTEGRATE, OP_CAMERA, OP_ADJOINT, OP_ADAPTIVE = 1, 2, 3, 4
 MAX_SPACETIMES = 64
 
 # Algorithmic FP64 flops of one RK4 step of one lane as implemented (static count of
@@ -41,6 +41,8 @@ MAX_SPACETIMES = 64
 # fma 2, sincos 2): Christoffel form, and Hamilton's equations.
 FLOPS_PER_STEP_F64 = 522
 FLOPS_PER_STEP_F64_HAM = 336
+# one Dormand-Prince 5(4) attempt (six right-hand sides and the tableau; csrc/dp45.hpp)
+FLOPS_PER_ATTEMPT_DP45 = 1036
 
 
 class MalbecError(RuntimeError):
@@ -87,6 +89,14 @@ class c_camera(C.Structure):
                 ("pad_", C.c_int32)]
 
 
+class c_adaptive(C.Structure):
+    _fields_ = [("tau_end", C.c_double), ("rtol", C.c_double), ("atol", C.c_double),
+                ("fac", C.c_double), ("facmin", C.c_double), ("facmax", C.c_double),
+                ("max_attempts", C.c_int64), ("horizon_factor", C.c_double),
+                ("r_escape", C.c_double), ("block", C.c_int32), ("persistent", C.c_int32),
+                ("steps_per_chunk", C.c_int32), ("pad_", C.c_int32)]
+
+
 EXPORTS = {
     "malbec_last_error": (C.c_char_p, []),
     "malbec_version": (C.c_int, []),
@@ -100,6 +110,10 @@ EXPORTS = {
                                       C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "malbec_invariants": (C.c_int, [C.POINTER(c_batch), C.c_int64, C.c_void_p, C.c_void_p,
                                     C.c_void_p]),
+    "malbec_integrate_adaptive": (C.c_int, [C.POINTER(c_adaptive), C.POINTER(c_batch), C.c_int64,
+                                            C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                            C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
+                                            C.c_void_p]),
     "malbec_integrate_record": (C.c_int, [C.POINTER(c_run), C.POINTER(c_batch), C.c_int64,
                                           C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                           C.c_void_p, C.c_void_p]),
@@ -270,6 +284,34 @@ def invariants(state: torch.Tensor, spacetimes, st_of_lane: Optional[torch.Tenso
     _check(lib().malbec_invariants(C.byref(b.c), n, _ptr(state, torch.float64, 8 * n, "state"),
                                    _ptr(out, torch.float64, 4 * n, "out"), _stream()))
     return out
+
+
+def integrate_adaptive(state: torch.Tensor, tau: torch.Tensor, h: torch.Tensor,
+                       status: torch.Tensor, steps: torch.Tensor, rejects: torch.Tensor,
+                       spacetimes, tau_end: float, rtol: float = 1e-10, atol: float = 1e-10,
+                       fac: float = 0.9, facmin: float = 0.2, facmax: float = 5.0,
+                       max_attempts: int = 1 << 20, horizon_factor: float = 1.01,
+                       r_escape: float = 1500.0, block: int = 0, persistent: bool = True,
+                       steps_per_chunk: int = 0, st_of_lane: Optional[torch.Tensor] = None,
+                       ws: Optional[torch.Tensor] = None):
+    """Dormand-Prince 5(4) with per-lane step size up to tau_end; state[8, n], tau and h
+    (float64[n]), status, steps and rejects (int32[n]) in/out."""
+    n = state.shape[-1]
+    ad = c_adaptive(tau_end, rtol, atol, fac, facmin, facmax, max_attempts, horizon_factor,
+                    r_escape, block, int(persistent), steps_per_chunk, 0)
+    b = _Batch(_spacetimes(spacetimes), st_of_lane, n)
+    need = workspace_bytes(OP_ADAPTIVE, n, int(persistent))
+    if need and ws is None:
+        ws = torch.empty(need, dtype=torch.uint8, device=state.device)
+    _check(lib().malbec_integrate_adaptive(C.byref(ad), C.byref(b.c), n,
+                                           _ptr(state, torch.float64, 8 * n, "state"),
+                                           _ptr(tau, torch.float64, n, "tau"),
+                                           _ptr(h, torch.float64, n, "h"),
+                                           _ptr(status, torch.int32, n, "status"),
+                                           _ptr(steps, torch.int32, n, "steps"),
+                                           _ptr(rejects, torch.int32, n, "rejects"),
+                                           _ptr(ws), ws.numel() if ws is not None else 0,
+                                           _stream()))
 
 
 def integrate_record(state: torch.Tensor, status: torch.Tensor, steps: torch.Tensor, spacetimes,

@@ -1,0 +1,233 @@
+// Adaptive FP64 integration with the Dormand-Prince 5(4) pair (csrc/dp45.hpp) and a
+// per-lane step size.  Each lane advances its affine parameter tau towards tau_end
+// in attempts; an attempt is accepted when the weighted RMS of the embedded error
+// estimate is <= 1, and the next step size follows the standard controller
+// h_new = h min(facmax', max(facmin, fac err^(-1/5))) (facmax' = 1 right after a
+// rejection).  The last attempt of a call is shortened to land on tau_end.  Stop
+// rules as in malbec_integrate, applied to attempts: a stage point at r <= r_stop
+// ends the lane as HORIZON and a non-finite or off-range result or error as
+// NONFINITE (start state kept); an accepted step that reaches r <= r_stop or
+// r >= r_escape ends it as HORIZON or ESCAPE; max_attempts attempts in one call
+// without reaching tau_end end it as BUDGET.
+//
+// Lanes need different numbers of attempts, so the work-queue driver of
+// persistent.hpp (one attempt per "step") keeps the wavefronts full; a
+// one-thread-per-lane kernel gives the same bits.
+#include "dp45.hpp"
+#include "internal.hpp"
+#include "persistent.hpp"
+
+namespace malbec {
+
+namespace {
+
+struct AdArgs {
+    int64_t n;
+    double *state;
+    double *tau;
+    double *h;
+    int32_t *status;
+    int32_t *steps;
+    int32_t *rejects;
+    const int32_t *st_of_lane;
+    double tau_end, rtol, atol, fac, facmin, facmax, r_escape;
+    int64_t max_attempts;
+};
+
+struct AdProg {
+    const AdArgs &A;
+    const Spacetime *table;
+    bool multi;
+    int32_t n_st;
+    struct Lane {
+        double y[8];
+        Deriv<double> k1;
+        Spacetime S;
+        double tau, h, facmax;
+        int64_t attempts;
+        int32_t st, acc, rej;
+    };
+    __device__ __forceinline__ void deriv0(Lane &L)
+    {
+        AccelF64 f{L.S.M, L.S.a, {0.0, 0.0, 1.0}};
+        for (int c = 0; c < 4; ++c) L.k1.u[c] = L.y[4 + c];
+        f(0, L.y[1], L.y[2], L.y[4], L.y[5], L.y[6], L.y[7], L.k1.acc[0], L.k1.acc[1], L.k1.acc[2],
+          L.k1.acc[3]);
+    }
+    __device__ __forceinline__ bool load(int64_t i, Lane &L)
+    {
+        L.st = A.status[i];
+        if (L.st != kActive) return false;
+        int32_t sid = 0;
+        if (multi) {
+            sid = A.st_of_lane[i];
+            if (sid < 0 || sid >= n_st) {
+                A.status[i] = kNonfinite;
+                return false;
+            }
+        }
+        L.S = table[sid];
+        L.tau = A.tau[i];
+        if (!(L.tau < A.tau_end)) return false;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) L.y[k] = A.state[k * A.n + i];
+        L.h = A.h[i];
+        L.facmax = A.facmax;
+        L.attempts = 0;
+        L.acc = 0;
+        L.rej = 0;
+        deriv0(L);
+        return true;
+    }
+    // one attempt; true when the lane is finished for this call
+    __device__ __forceinline__ bool step(Lane &L)
+    {
+        if (L.attempts == A.max_attempts) {
+            L.st = kBudget;
+            return true;
+        }
+        ++L.attempts;
+        double hh = L.h;
+        bool last = false;
+        if (L.tau + hh >= A.tau_end) {
+            hh = A.tau_end - L.tau;
+            last = true;
+        }
+        // stage 0 of the rotation base is the start point: sin and cos evaluated fresh
+        AccelF64 f{L.S.M, L.S.a, {0.0, 0.0, 1.0}};
+        {
+            double s, c;
+            f.trig(0, L.y[2], s, c);
+        }
+        double y1[8], e[8], sr[5];
+        Deriv<double> k7;
+        dp45_attempt(f, hh, L.y, L.k1, y1, e, k7, sr);
+        const double rs = L.S.r_stop;
+        if (sr[0] <= rs || sr[1] <= rs || sr[2] <= rs || sr[3] <= rs || sr[4] <= rs) {
+            L.st = kHorizon;
+            return true;
+        }
+        double sum = 0.0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const double sc = fma(A.rtol, fmax(fabs(L.y[c]), fabs(y1[c])), A.atol);
+            const double q = e[c] / sc;
+            sum = fma(q, q, sum);
+        }
+        const double err = sqrt(sum * 0.125);
+        if (!usable(y1) || !__builtin_isfinite(err)) {
+            L.st = kNonfinite;
+            return true;
+        }
+        const double grow = err > 0.0 ? A.fac * pow(err, -0.2) : A.facmax;
+        if (err <= 1.0) {
+#pragma unroll
+            for (int c = 0; c < 8; ++c) L.y[c] = y1[c];
+            L.k1 = k7;
+            L.tau = last ? A.tau_end : L.tau + hh;
+            ++L.acc;
+            L.h = hh * fmin(L.facmax, fmax(A.facmin, grow));
+            L.facmax = A.facmax;
+            if (L.y[1] <= rs) L.st = kHorizon;
+            else if (L.y[1] >= A.r_escape) L.st = kEscape;
+        } else {
+            ++L.rej;
+            L.h = hh * fmin(1.0, fmax(A.facmin, grow));
+            L.facmax = 1.0;
+        }
+        return L.st != kActive || !(L.tau < A.tau_end);
+    }
+    __device__ __forceinline__ void store(int64_t i, const Lane &L)
+    {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) A.state[k * A.n + i] = L.y[k];
+        A.tau[i] = L.tau;
+        A.h[i] = L.h;
+        A.status[i] = L.st;
+        A.steps[i] += L.acc;
+        A.rejects[i] += L.rej;
+    }
+};
+
+template <bool MULTI>
+__global__ void __launch_bounds__(256) dp45_kernel(AdArgs A, StTable T)
+{
+    __shared__ Spacetime lds_st[kMaxSt];
+    for (int k = threadIdx.x; k < T.n_st; k += blockDim.x) lds_st[k] = T.st[k];
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    AdProg P{A, lds_st, MULTI, T.n_st};
+    AdProg::Lane L;
+    if (!P.load(i, L)) return;
+    while (!P.step(L)) {
+    }
+    P.store(i, L);
+}
+
+template <bool MULTI>
+__global__ void __launch_bounds__(256) dp45_persistent_kernel(AdArgs A, StTable T,
+                                                              unsigned long long *counter,
+                                                              int32_t chunk)
+{
+    __shared__ Spacetime lds_st[kMaxSt];
+    for (int k = threadIdx.x; k < T.n_st; k += blockDim.x) lds_st[k] = T.st[k];
+    __syncthreads();
+    AdProg P{A, lds_st, MULTI, T.n_st};
+    persistent_loop(P, A.n, counter, chunk);
+}
+
+}  // namespace
+
+int launch_adaptive(const malbec_adaptive &ad, const StTable &T, const int32_t *st_of_lane,
+                    int64_t n, double *state, double *tau, double *h, int32_t *status,
+                    int32_t *steps, int32_t *rejects, void *ws, hipStream_t s)
+{
+    const int block = ad.block > 0 ? ad.block : 256;
+    if (block > 256) return fail(MALBEC_EINVAL, "block %d exceeds the kernel's launch bound 256", block);
+    const bool multi = st_of_lane != nullptr && T.n_st > 1;
+    AdArgs A;
+    A.n = n;
+    A.state = state;
+    A.tau = tau;
+    A.h = h;
+    A.status = status;
+    A.steps = steps;
+    A.rejects = rejects;
+    A.st_of_lane = multi ? st_of_lane : nullptr;
+    A.tau_end = ad.tau_end;
+    A.rtol = ad.rtol;
+    A.atol = ad.atol;
+    A.fac = ad.fac;
+    A.facmin = ad.facmin;
+    A.facmax = ad.facmax;
+    A.r_escape = ad.r_escape;
+    A.max_attempts = ad.max_attempts;
+    if (ad.persistent) {
+        const int32_t sub = ad.steps_per_chunk > 0 ? ad.steps_per_chunk : 8;
+        int grid = 0;
+        int rc = persistent_grid(multi ? (const void *)dp45_persistent_kernel<true>
+                                       : (const void *)dp45_persistent_kernel<false>,
+                                 block, n, grid);
+        if (rc) return rc;
+        unsigned long long *counter = (unsigned long long *)ws;
+        hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(1), 0, s, counter);
+        MALBEC_LAUNCH_CHECK("zero_u64_kernel");
+        if (multi)
+            hipLaunchKernelGGL((dp45_persistent_kernel<true>), dim3(grid), dim3(block), 0, s, A, T,
+                               counter, sub);
+        else
+            hipLaunchKernelGGL((dp45_persistent_kernel<false>), dim3(grid), dim3(block), 0, s, A, T,
+                               counter, sub);
+        MALBEC_LAUNCH_CHECK("dp45_persistent_kernel");
+        return MALBEC_OK;
+    }
+    if (multi)
+        hipLaunchKernelGGL((dp45_kernel<true>), dim3(grid_for(n, block)), dim3(block), 0, s, A, T);
+    else
+        hipLaunchKernelGGL((dp45_kernel<false>), dim3(grid_for(n, block)), dim3(block), 0, s, A, T);
+    MALBEC_LAUNCH_CHECK("dp45_kernel");
+    return MALBEC_OK;
+}
+
+}  // namespace malbec

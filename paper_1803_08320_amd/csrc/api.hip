@@ -75,7 +75,8 @@ int malbec_version(void) { return 10000 * 0 + 100 * 3 + 0; }
 size_t malbec_workspace_bytes(int32_t op, int64_t n, int32_t aux)
 {
     if (op == MALBEC_OP_CAMERA) return 256;  // work counter (own cache line)
-    if (op == MALBEC_OP_INTEGRATE && aux) return 256;  // persistent kernel's work counter
+    if ((op == MALBEC_OP_INTEGRATE || op == MALBEC_OP_ADAPTIVE) && aux)
+        return 256;  // persistent kernel's work counter
     if (op == MALBEC_OP_ADJOINT && n > 0 && aux > 0) return (size_t)aux * 8 * (size_t)n * sizeof(double);
     return 0;
 }
@@ -261,6 +262,40 @@ int malbec_invariants(const malbec_batch *b, int64_t n, const double *state, dou
     if (rc) return rc;
     if (n == 0) return MALBEC_OK;
     return launch_invariants(T, b->st_of_lane, n, state, out, (hipStream_t)stream);
+}
+
+int malbec_integrate_adaptive(const malbec_adaptive *ad, const malbec_batch *b, int64_t n,
+                              double *state, double *tau, double *h, int32_t *status,
+                              int32_t *steps, int32_t *rejects, void *ws, size_t ws_bytes,
+                              void *stream)
+{
+    clear_error();
+    if (!ad) return fail(MALBEC_EINVAL, "ad is NULL");
+    if (n < 0) return fail(MALBEC_EINVAL, "n = %lld < 0", (long long)n);
+    if (n > 0 && (!state || !tau || !h || !status || !steps || !rejects))
+        return fail(MALBEC_EINVAL, "state, tau, h, status, steps and rejects must be non-NULL");
+    if (n > ((int64_t)1 << 40)) return fail(MALBEC_EINVAL, "n too large");
+    if (!isfinite(ad->tau_end)) return fail(MALBEC_EINVAL, "tau_end must be finite");
+    if (!(ad->rtol > 0.0) || !(ad->atol > 0.0) || !isfinite(ad->rtol) || !isfinite(ad->atol))
+        return fail(MALBEC_EINVAL, "rtol and atol must be finite and > 0");
+    if (!(ad->fac > 0.0 && ad->fac <= 1.0)) return fail(MALBEC_EINVAL, "fac must be in (0, 1]");
+    if (!(ad->facmin > 0.0 && ad->facmin <= 1.0 && ad->facmax >= 1.0 && isfinite(ad->facmax)))
+        return fail(MALBEC_EINVAL, "need 0 < facmin <= 1 <= facmax");
+    if (ad->max_attempts < 1) return fail(MALBEC_EINVAL, "max_attempts must be >= 1");
+    if (!(ad->r_escape > 0.0)) return fail(MALBEC_EINVAL, "r_escape must be > 0");
+    if (ad->block < 0 || ad->block > 1024 || (ad->block % 64) != 0)
+        return fail(MALBEC_EINVAL, "block = %d must be a multiple of 64 in [64, 1024] or 0", ad->block);
+    if (ad->persistent != 0 && ad->persistent != 1) return fail(MALBEC_EINVAL, "persistent must be 0 or 1");
+    if (ad->steps_per_chunk < 0) return fail(MALBEC_EINVAL, "steps_per_chunk < 0");
+    size_t need = malbec_workspace_bytes(MALBEC_OP_ADAPTIVE, n, ad->persistent);
+    if (ws_bytes < need || (need > 0 && !ws))
+        return fail(MALBEC_ENOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, need);
+    StTable T;
+    int rc = make_table(b, ad->horizon_factor, 1.0, T);
+    if (rc) return rc;
+    if (n == 0) return MALBEC_OK;
+    return launch_adaptive(*ad, T, b->st_of_lane, n, state, tau, h, status, steps, rejects, ws,
+                           (hipStream_t)stream);
 }
 
 int malbec_integrate_record(const malbec_run *run, const malbec_batch *b, int64_t n, double *state,

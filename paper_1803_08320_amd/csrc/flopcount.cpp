@@ -30,6 +30,7 @@ inline Counted recip(Counted x) { ++g_div; g_flops += 1; return Counted(1.0 / x.
 }
 
 #include <cmath>
+#include "dp45.hpp"
 #include "ham_accel.hpp"
 #include "kerr_accel.hpp"
 
@@ -82,5 +83,16 @@ int main()
     malbec::rk4_ham_step(hf, Counted(0.02), z, z1, sr);
     std::printf("ham_rhs_flops %ld\nham_step_flops %ld\nham_step_fma %ld\nham_step_addmul %ld\nham_step_div %ld\n",
                 hrhs, g_flops, g_fma, g_addmul, g_div);
+
+    // one Dormand-Prince attempt (six right-hand sides, the stage points, the
+    // 5th-order result and the error estimate; the controller's few operations and
+    // the pow are not counted)
+    malbec::Deriv<Counted> k1, k7;
+    for (int c = 0; c < 4; ++c) k1.u[c] = y[4 + c];
+    f(0, y[1], y[2], y[4], y[5], y[6], y[7], k1.acc[0], k1.acc[1], k1.acc[2], k1.acc[3]);
+    Counted e[8], sr5[5];
+    g_flops = g_div = g_fma = g_addmul = 0;
+    malbec::dp45_attempt(f, Counted(0.02), y, k1, y1, e, k7, sr5);
+    std::printf("dp45_attempt_flops %ld\n", g_flops);
     return 0;
 }

@@ -63,6 +63,9 @@ int launch_invariants(const StTable &T, const int32_t *st_of_lane, int64_t n,
                       const double *state, double *out, hipStream_t s);
 int launch_convert(const StTable &T, const int32_t *st_of_lane, int64_t n, double *state,
                    int32_t to_momenta, hipStream_t s);
+int launch_adaptive(const malbec_adaptive &ad, const StTable &T, const int32_t *st_of_lane,
+                    int64_t n, double *state, double *tau, double *h, int32_t *status,
+                    int32_t *steps, int32_t *rejects, void *ws, hipStream_t s);
 int launch_integrate_record(const malbec_run &run, const StTable &T, const int32_t *st_of_lane,
                             int64_t n, double *state, int32_t *status, int32_t *steps,
                             int32_t record_every, double *traj, hipStream_t s);

@@ -48,7 +48,8 @@ def test_struct_layout_matches_header(m, tmp_path):
                    "#define P(T) printf(#T \" %zu\\n\", sizeof(T));\n"
                    "#define O(T, f) printf(#T \".\" #f \" %zu\\n\", offsetof(T, f));\n"
                    "int main(void){P(malbec_spacetime)P(malbec_batch)P(malbec_ic_spec)"
-                   "P(malbec_run)P(malbec_camera)O(malbec_ic_spec, rows)O(malbec_ic_spec, max_attempts)"
+                   "P(malbec_run)P(malbec_camera)P(malbec_adaptive)O(malbec_adaptive, max_attempts)"
+                   "O(malbec_adaptive, steps_per_chunk)O(malbec_ic_spec, rows)O(malbec_ic_spec, max_attempts)"
                    "O(malbec_run, checkpoint_every)O(malbec_run, persistent)O(malbec_run, formulation)"
                    "O(malbec_camera, max_steps)O(malbec_camera, persistent)"
                    "O(malbec_batch, st_of_lane)return 0;}\n")
@@ -61,6 +62,9 @@ def test_struct_layout_matches_header(m, tmp_path):
     assert int(got["malbec_ic_spec"]) == C.sizeof(m.c_ic_spec)
     assert int(got["malbec_run"]) == C.sizeof(m.c_run)
     assert int(got["malbec_camera"]) == C.sizeof(m.c_camera)
+    assert int(got["malbec_adaptive"]) == C.sizeof(m.c_adaptive)
+    assert int(got["malbec_adaptive.max_attempts"]) == m.c_adaptive.max_attempts.offset
+    assert int(got["malbec_adaptive.steps_per_chunk"]) == m.c_adaptive.steps_per_chunk.offset
     assert int(got["malbec_ic_spec.rows"]) == m.c_ic_spec.rows.offset
     assert int(got["malbec_ic_spec.max_attempts"]) == m.c_ic_spec.max_attempts.offset
     assert int(got["malbec_run.checkpoint_every"]) == m.c_run.checkpoint_every.offset
@@ -178,6 +182,29 @@ def test_init_and_camera_argument_errors(m):
     assert m.version() >= 300
 
 
+def _adaptive(m, **kw):
+    d = dict(tau_end=10.0, rtol=1e-9, atol=1e-9, fac=0.9, facmin=0.2, facmax=5.0,
+             max_attempts=100, horizon_factor=1.01, r_escape=1500.0, block=0, persistent=0,
+             steps_per_chunk=0, pad_=0)
+    d.update(kw)
+    return m.c_adaptive(**d)
+
+
+@pytest.mark.parametrize("kw,expect", [
+    (dict(rtol=0.0), -1), (dict(atol=-1.0), -1), (dict(fac=1.5), -1), (dict(facmin=0.0), -1),
+    (dict(facmax=0.5), -1), (dict(max_attempts=0), -1), (dict(tau_end=float("inf")), -1),
+    (dict(block=100), -1), (dict(persistent=3), -1), (dict(persistent=1), -2),
+    (dict(horizon_factor=0.5), -1),
+])
+def test_adaptive_argument_errors(m, kw, expect):
+    ad = _adaptive(m, **kw)
+    arr, b = _batch(m)
+    rc = m.lib().malbec_integrate_adaptive(C.byref(ad), C.byref(b), 4, FAKE, FAKE, FAKE, FAKE,
+                                           FAKE, FAKE, None, 0, None)
+    assert rc == expect, m.last_error()
+    assert m.workspace_bytes(m.OP_ADAPTIVE, 10, 1) >= 8
+
+
 def test_flop_count_constant(m, tmp_path):
     """The roofline's flops per lane-step equal the static count of the templates the
     kernels instantiate."""
@@ -188,3 +215,4 @@ def test_flop_count_constant(m, tmp_path):
     vals = dict(l.split() for l in out.strip().split("\n"))
     assert int(vals["step_flops"]) == m.FLOPS_PER_STEP_F64
     assert int(vals["ham_step_flops"]) == m.FLOPS_PER_STEP_F64_HAM
+    assert int(vals["dp45_attempt_flops"]) == m.FLOPS_PER_ATTEMPT_DP45

@@ -16,6 +16,7 @@ KERR_RANGES = ((5.0, 50.0), (math.pi / 4, 3 * math.pi / 4), (0.92, 0.98), (2.5, 
 
 SRC = r"""
 #include <cmath>
+#include "dp45.hpp"
 #include "ham_accel.hpp"
 #include "kerr_accel.hpp"
 struct Chr {
@@ -49,6 +50,14 @@ extern "C" void chr_step(double M, double a, double h, const double *y, double *
     double sr[3];
     malbec::rk4_step(f, h, y, y1, sr);
 }
+extern "C" void dp45(double M, double a, double h, const double *y, double *y1, double *e) {
+    Chr f{M, a};
+    malbec::Deriv<double> k1, k7;
+    for (int c = 0; c < 4; ++c) k1.u[c] = y[4 + c];
+    f(0, y[1], y[2], y[4], y[5], y[6], y[7], k1.acc[0], k1.acc[1], k1.acc[2], k1.acc[3]);
+    double sr[5];
+    malbec::dp45_attempt(f, h, y, k1, y1, e, k7, sr);
+}
 extern "C" void ham_step(double M, double a, double h, const double *z, double *z1) {
     Ham f{M, a, malbec::ham_const(a, z[4], z[7])};
     double sr[3];
@@ -72,6 +81,7 @@ def host(tmp_path_factory):
         getattr(lib, name).argtypes = [C.c_double, C.c_double, dp, dp]
     for name in ("chr_step", "ham_step"):
         getattr(lib, name).argtypes = [C.c_double, C.c_double, C.c_double, dp, dp]
+    lib.dp45.argtypes = [C.c_double, C.c_double, C.c_double, dp, dp, dp]
     return lib
 
 
@@ -126,3 +136,19 @@ def test_rk4_steps_match_oracle(orc, host, a):
         host.ham_step(1.0, a, 0.02, _p(np.ascontiguousarray(z0[:, i])), _p(z1))
         assert np.max(np.abs(z1 - refh[:, i]) / (np.abs(refh[:, i]) + 1.0)) <= 1e-14
         assert z1[4] == z0[4, i] and z1[7] == z0[7, i]
+
+
+@pytest.mark.parametrize("a", [0.0, 0.9])
+def test_dp45_attempt_matches_oracle(orc, host, a):
+    """One Dormand-Prince attempt: 5th-order result and embedded error estimate."""
+    s0 = sample_states(orc, a, 64, 53)
+    for i in range(s0.shape[1]):
+        y = np.ascontiguousarray(s0[:, i])
+        for h in (0.05, 0.8):
+            y1, e = np.zeros(8), np.zeros(8)
+            host.dp45(1.0, a, h, _p(y), _p(y1), _p(e))
+            ry1, re = orc.dp45_attempt(1.0, a, h, y)
+            assert np.max(np.abs(y1 - ry1) / (np.abs(ry1) + 1.0)) <= 1e-14
+            # e is a difference of two solutions (cancellation): its rounding is
+            # absolute, ~ h ulp(f)
+            assert np.max(np.abs(e - re)) <= 1e-14 * h * (np.max(np.abs(y[4:])) + 1.0)
