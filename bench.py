@@ -73,6 +73,7 @@ def parse():
     p.add_argument("--no-ham", action="store_true", help="skip the Hamiltonian-form leg")
     p.add_argument("--no-traj", action="store_true", help="skip the trajectory-output leg")
     p.add_argument("--no-adaptive", action="store_true", help="skip the adaptive (DP45) leg")
+    p.add_argument("--no-grid", action="store_true", help="skip the gridded 3+1 metric leg")
     p.add_argument("--no-extra", action="store_true",
                    help="skip the camera, mixed-spin batch and adjoint legs")
     p.add_argument("--probe-copy-bytes", type=int, default=0,
@@ -340,6 +341,40 @@ def main():
             / PEAK_FP64_VECTOR_TFLOPS,
             "dE_over_E_p99": float(np.quantile(np.abs(j1[0] / i0[0] - 1)[actd], 0.99)),
             "dQ_over_Q_p99": float(np.quantile(np.abs(j1[2] / i0[2] - 1)[qd], 0.99))}
+
+    if not args.no_grid:
+        # the same orbits in Kerr sampled in 3+1 form on a 801 x 401 (r, theta) grid
+        # (Section 2): Hamilton's equations with the interpolated metric, 2,000 steps
+        n_g = 2000
+        g = m.grid_kerr(1.0, 0.9, 801, 401, 1.5, 60.0 / 800, 0.1, (math.pi - 0.2) / 400,
+                        1.2 * (1.0 + math.sqrt(1.0 - 0.81)))
+        z0 = s0.clone()
+        m.convert_state(z0, st, True)
+        ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+
+        def run_grid(record):
+            state.copy_(z0)
+            status.zero_()
+            steps.zero_()
+            if record:
+                ev[0].record()
+            m.integrate_grid(state, status, steps, g, h, n_g, 55.0, block=args.block)
+            if record:
+                ev[1].record()
+        run_grid(False)
+        torch.cuda.synchronize()
+        run_grid(True)
+        torch.cuda.synchronize()
+        dt = ev[0].elapsed_time(ev[1]) / 1e3
+        ls = int(steps.sum().item())
+        result["grid_3p1"] = {
+            "value": ls / dt, "unit": "lane-steps/s", "grid": [801, 401],
+            "rk4_steps": n_g, "kernel_ms": 1e3 * dt,
+            "vs_analytic_hamiltonian": (ls / dt) / result["hamiltonian"]["value"]
+            if "hamiltonian" in result else None,
+            "gathered_bytes_per_lane_step": 4 * 16 * 40,
+            "gather_GB_per_s": 4 * 16 * 40 * ls / dt / 1e9,
+            "active_frac": float((status == 0).float().mean().item())}
 
     if not args.no_extra:
         result["extra"] = extra_legs(m, torch, np)

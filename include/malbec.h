@@ -161,6 +161,19 @@ typedef struct {
     int32_t pad_;
 } malbec_adaptive;
 
+/* A stationary, axisymmetric metric in 3+1 form (Section 2, eq. ADM) sampled on a
+ * uniform (r, theta) grid: shift beta = (0, 0, beta^phi), diagonal spatial metric.
+ * Node (i, j) sits at r = r0 + i dr, theta = th0 + j dth and holds five doubles,
+ * nodes[(i * nth + j) * 5 + k], k = (alpha, beta^phi, gamma_rr, gamma_thth,
+ * gamma_phph / sin^2 theta). */
+typedef struct {
+    int32_t nr, nth;     /* nodes in r and theta, >= 4 each */
+    double r0, dr;       /* dr > 0 */
+    double th0, dth;     /* dth > 0; th0 > 0 and th0 + (nth - 1) dth < pi */
+    double r_stop;       /* lanes stop at r <= r_stop (e.g. 1.01 r_+); >= r0 + dr */
+    const double *nodes; /* device, nr * nth * 5 doubles */
+} malbec_grid;
+
 /* Camera (malbec_trace_camera): Bardeen image plane of a static observer at
  * (r_obs, theta = incl, phi = 0); pixel p = j * nx + i, alpha = -w + (i + 1/2) 2w / nx,
  * beta = -w + (j + 1/2) 2w / ny.  Photon: E = 1, L_z = -alpha sin(incl),
@@ -287,6 +300,32 @@ MALBEC_API int malbec_integrate_adaptive(const malbec_adaptive *ad, const malbec
                                          int64_t n, double *state, double *tau, double *h,
                                          int32_t *status, int32_t *steps, int32_t *rejects,
                                          void *ws, size_t ws_bytes, void *stream);
+
+/* Fill g->nodes (device, written through the pointer passed as `nodes`, which must be
+ * g->nodes) with the 3+1 functions of Kerr given in Section 2: alpha =
+ * sqrt(rho^2 Delta / Sigma), beta^phi = -2 M a r / Sigma, gamma_rr = rho^2 / Delta,
+ * gamma_thth = rho^2, gamma_phph / sin^2 theta = Sigma / rho^2 (the test metric of the
+ * gridded path).  Errors: MALBEC_EINVAL, MALBEC_EDEVICE. */
+MALBEC_API int malbec_grid_fill_kerr(const malbec_grid *g, double M, double a, double *nodes,
+                                     void *stream);
+
+/* Fixed-step RK4 of Hamilton's equations (Section 2, eq. Ham) in the gridded 3+1
+ * metric g: the five functions and their r, theta derivatives are the tensor-product
+ * 4-point Lagrange interpolant of the grid (stencil of nodes i-1 .. i+2 around the
+ * point's cell, shifted inwards at the edges), the inverse metric is g^tt =
+ * -1/alpha^2, g^tphi = beta^phi / alpha^2, g^phph = 1/gamma_phph - (beta^phi)^2 /
+ * alpha^2, g^rr = 1/gamma_rr, g^thth = 1/gamma_thth.  state: device 8n, (x^mu, p_mu)
+ * (run->formulation must be MALBEC_FORM_HAMILTONIAN); status, steps as in
+ * malbec_integrate.  Stops after each step, the first RK4 stage point (in order) that
+ * is at r <= g->r_stop (HORIZON) or outside the grid's interior [r0 + dr,
+ * r0 + (nr - 2) dr] x [th0 + dth, th0 + (nth - 2) dth] (NONFINITE) deciding, both with
+ * the start state kept; a non-finite or off-grid result (NONFINITE, start state kept);
+ * r <= r_stop (HORIZON); r >= run->r_escape (ESCAPE), which must lie inside the grid.
+ * run: h, n_steps, block, steps_per_chunk, r_escape are used; precision F64,
+ * persistent 0, no checkpoints.  Errors: MALBEC_EINVAL, MALBEC_ENOTSUP, MALBEC_EDEVICE. */
+MALBEC_API int malbec_integrate_grid(const malbec_run *run, const malbec_grid *g, int64_t n,
+                                     double *state, int32_t *status, int32_t *steps,
+                                     void *stream);
 
 /* Convert n states in place between the two formulations: to_momenta = 1 lowers
  * the index, (x, u^mu) -> (x, p_mu = g_{mu nu} u^nu); to_momenta = 0 raises it,

@@ -84,6 +84,12 @@ def lib():
                                        C.c_int, C.c_int]),
         "oracle_invariants": (C.c_int, [P(d), vp, i64, P(d), P(d)]),
         "oracle_dp45_attempt": (None, [d, d, d, P(d), P(d), P(d)]),
+        "oracle_kerr_3p1": (None, [d, d, d, d, P(d)]),
+        "oracle_grid_fill_kerr": (None, [d, d, i64, i64, d, d, d, d, P(d)]),
+        "oracle_grid_eval": (None, [i64, i64, d, d, d, d, P(d), d, d, P(d), P(d), P(d)]),
+        "oracle_grid_rhs": (None, [i64, i64, d, d, d, d, P(d), P(d), P(d)]),
+        "oracle_integrate_grid": (C.c_int, [i64, i64, d, d, d, d, P(d), i64, P(d), P(i32), P(i32),
+                                            d, i64, d, d, C.c_int]),
         "oracle_integrate_adaptive": (C.c_int, [P(d), vp, i64, P(d), P(d), P(d), P(i32), P(i32),
                                                 P(i32), d, d, d, d, d, d, i64, d, d, C.c_int]),
         "oracle_camera_ic": (None, [d, d, d, d, d, i64, i64, i64, i64, P(d)]),
@@ -270,6 +276,56 @@ def dp45_attempt(M, a, h, y):
     y1, e = np.zeros(8), np.zeros(8)
     lib().oracle_dp45_attempt(M, a, h, _dp(y), _dp(y1), _dp(e))
     return y1, e
+
+
+class Grid:
+    """A uniform (r, theta) grid of the 3+1 functions (alpha, beta^phi, gamma_rr,
+    gamma_thth, gamma_phph / sin^2 theta), nodes[i, j, k]."""
+
+    def __init__(self, nodes, r0, dr, th0, dth):
+        self.nodes = np.ascontiguousarray(nodes, dtype=np.float64)
+        self.nr, self.nth = self.nodes.shape[:2]
+        self.r0, self.dr, self.th0, self.dth = float(r0), float(dr), float(th0), float(dth)
+
+    def args(self):
+        return (self.nr, self.nth, self.r0, self.dr, self.th0, self.dth, _dp(self.nodes.reshape(-1)))
+
+
+def kerr_3p1(M, a, r, th):
+    F = np.zeros(5)
+    lib().oracle_kerr_3p1(M, a, r, th, _dp(F))
+    return F
+
+
+def grid_kerr(M, a, nr, nth, r0, dr, th0, dth):
+    nodes = np.zeros(nr * nth * 5)
+    lib().oracle_grid_fill_kerr(M, a, nr, nth, r0, dr, th0, dth, _dp(nodes))
+    return Grid(nodes.reshape(nr, nth, 5), r0, dr, th0, dth)
+
+
+def grid_eval(grid, r, th):
+    F, Fr, Ft = np.zeros(5), np.zeros(5), np.zeros(5)
+    lib().oracle_grid_eval(*grid.args(), r, th, _dp(F), _dp(Fr), _dp(Ft))
+    return F, Fr, Ft
+
+
+def grid_rhs(grid, z):
+    z = _f64(z)
+    f = np.zeros(8)
+    lib().oracle_grid_rhs(*grid.args(), _dp(z), _dp(f))
+    return f
+
+
+def integrate_grid(grid, state, h, n_steps, r_stop, r_escape, status=None, steps=None, nthreads=0):
+    """Canonical RK4 on the gridded metric (copies); returns (state, status, steps)."""
+    state = np.array(state, dtype=np.float64, copy=True)
+    n = state.shape[1]
+    s = np.ascontiguousarray(state.reshape(-1))
+    status = np.zeros(n, np.int32) if status is None else np.array(status, np.int32, copy=True)
+    steps = np.zeros(n, np.int32) if steps is None else np.array(steps, np.int32, copy=True)
+    lib().oracle_integrate_grid(*grid.args(), n, _dp(s), _ip(status), _ip(steps), h, n_steps,
+                                r_stop, r_escape, nthreads)
+    return s.reshape(8, n), status, steps
 
 
 def integrate_adaptive(spacetimes, state, tau_end, h0, rtol=1e-10, atol=1e-10, fac=0.9,

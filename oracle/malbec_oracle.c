@@ -618,6 +618,230 @@ int oracle_integrate_adaptive(const double *Ma, const int32_t *st_of_lane, int64
 }
 
 /* ================================================================================ */
+/* Numerical metrics in 3+1 form on an (r, theta) grid                                 */
+/* ================================================================================ */
+/* Section 2 writes the line element in 3+1 form, ds^2 = -alpha^2 dt^2 +
+ * gamma_ij (dx^i + beta^i dt)(dx^j + beta^j dt) (eq. ADM), gives alpha, beta^i and
+ * gamma_ij of Kerr, and names the 3+1 form as the way to numerical metrics.  A
+ * stationary, axisymmetric metric with beta = (0, 0, beta^phi) and diagonal gamma is
+ * given here by five functions of (r, theta) sampled on a uniform grid:
+ *   F = (alpha, beta^phi, gamma_rr, gamma_thth, gamma_phph / sin^2 theta),
+ * node (i, j) at r_i = r0 + i dr, theta_j = th0 + j dth, stored at
+ * nodes[(i nth + j) 5 + k].  Between nodes each function is the tensor product of
+ * the 4-point Lagrange interpolants in r and theta (nodes i-1 .. i+2 around the cell
+ * holding the point, the stencil shifted inwards at the grid's edges); its
+ * derivatives are those of the interpolant.  The inverse metric follows from the
+ * 3+1 quantities: g^tt = -1/alpha^2, g^tphi = beta^phi/alpha^2,
+ * g^phph = 1/gamma_phph - (beta^phi)^2/alpha^2, g^rr = 1/gamma_rr,
+ * g^thth = 1/gamma_thth, and the canonical equations (eq. Ham) are integrated with
+ * classic RK4 in (x^mu, p_mu). */
+
+/* Kerr in 3+1 form (Section 2): alpha = sqrt(rho^2 Delta / Sigma),
+ * beta^phi = -2 M a r / Sigma, gamma = diag(rho^2/Delta, rho^2, Sigma sin^2 / rho^2). */
+void oracle_kerr_3p1(double M, double a, double r, double th, double *F)
+{
+    double s = sin(th), c = cos(th);
+    double rho2 = r * r + a * a * c * c;
+    double Delta = r * r - 2.0 * M * r + a * a;
+    double Sigma = (r * r + a * a) * (r * r + a * a) - a * a * Delta * s * s;
+    F[0] = sqrt(rho2 * Delta / Sigma);
+    F[1] = -2.0 * M * a * r / Sigma;
+    F[2] = rho2 / Delta;
+    F[3] = rho2;
+    F[4] = Sigma / rho2;
+}
+
+void oracle_grid_fill_kerr(double M, double a, int64_t nr, int64_t nth, double r0, double dr,
+                           double th0, double dth, double *nodes)
+{
+    for (int64_t i = 0; i < nr; ++i)
+        for (int64_t j = 0; j < nth; ++j)
+            oracle_kerr_3p1(M, a, r0 + (double)i * dr, th0 + (double)j * dth, &nodes[(i * nth + j) * 5]);
+}
+
+/* Lagrange basis on the nodes -1, 0, 1, 2 at u, and its derivative in u. */
+static void lagrange4(double u, double w[4], double dw[4])
+{
+    const double x[4] = {-1.0, 0.0, 1.0, 2.0};
+    for (int k = 0; k < 4; ++k) {
+        double num = 1.0, den = 1.0, d = 0.0;
+        for (int m = 0; m < 4; ++m) {
+            if (m == k) continue;
+            den *= x[k] - x[m];
+            /* derivative of the product: sum over the factor left out */
+            double prod = 1.0;
+            for (int q = 0; q < 4; ++q)
+                if (q != k && q != m) prod *= u - x[q];
+            d += prod;
+            num *= u - x[m];
+        }
+        w[k] = num / den;
+        dw[k] = d / den;
+    }
+}
+
+/* Cell and offset of coordinate x on a grid of n nodes x0 + i h: the stencil starts
+ * at node i - 1 with i = floor((x - x0) / h) clamped to [1, n - 3]. */
+static int64_t grid_cell(double x, double x0, double h, int64_t n, double *u)
+{
+    double q = (x - x0) / h;
+    int64_t i = (int64_t)floor(q);
+    if (i < 1) i = 1;
+    if (i > n - 3) i = n - 3;
+    *u = q - (double)i;
+    return i;
+}
+
+/* F, dF/dr, dF/dtheta (5 functions each) at (r, theta). */
+void oracle_grid_eval(int64_t nr, int64_t nth, double r0, double dr, double th0, double dth,
+                      const double *nodes, double r, double th, double *F, double *Fr, double *Ft)
+{
+    double ur, ut, wr[4], dwr[4], wt[4], dwt[4];
+    int64_t i = grid_cell(r, r0, dr, nr, &ur);
+    int64_t j = grid_cell(th, th0, dth, nth, &ut);
+    lagrange4(ur, wr, dwr);
+    lagrange4(ut, wt, dwt);
+    for (int k = 0; k < 5; ++k) {
+        double v = 0.0, vr = 0.0, vt = 0.0;
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b) {
+                double f = nodes[((i - 1 + a) * nth + (j - 1 + b)) * 5 + k];
+                v += wr[a] * wt[b] * f;
+                vr += dwr[a] * wt[b] * f;
+                vt += wr[a] * dwt[b] * f;
+            }
+        F[k] = v;
+        Fr[k] = vr / dr;
+        Ft[k] = vt / dth;
+    }
+}
+
+typedef struct {
+    int64_t nr, nth;
+    double r0, dr, th0, dth;
+    const double *nodes;
+} grid_t;
+
+/* Inverse metric g^{mu nu} (4x4) and its r and theta derivatives from the gridded
+ * 3+1 functions at (r, theta). */
+static void grid_inverse_metric(const grid_t *g, double r, double th, double gi[4][4],
+                                double dgi[2][4][4])
+{
+    double F[5], Fd[2][5];
+    oracle_grid_eval(g->nr, g->nth, g->r0, g->dr, g->th0, g->dth, g->nodes, r, th, F, Fd[0], Fd[1]);
+    double s = sin(th), c = cos(th);
+    double al = F[0], be = F[1], grr = F[2], gtt = F[3], gpp = F[4] * s * s;
+    double d_al[2] = {Fd[0][0], Fd[1][0]}, d_be[2] = {Fd[0][1], Fd[1][1]};
+    double d_grr[2] = {Fd[0][2], Fd[1][2]}, d_gtt[2] = {Fd[0][3], Fd[1][3]};
+    double d_gpp[2] = {Fd[0][4] * s * s, Fd[1][4] * s * s + F[4] * 2.0 * s * c};
+    memset(gi, 0, 16 * sizeof(double));
+    memset(dgi, 0, 32 * sizeof(double));
+    double ia2 = 1.0 / (al * al);
+    gi[0][0] = -ia2;
+    gi[0][3] = gi[3][0] = be * ia2;
+    gi[3][3] = 1.0 / gpp - be * be * ia2;
+    gi[1][1] = 1.0 / grr;
+    gi[2][2] = 1.0 / gtt;
+    for (int l = 0; l < 2; ++l) {
+        double d_ia2 = -2.0 * d_al[l] / (al * al * al);
+        dgi[l][0][0] = -d_ia2;
+        dgi[l][0][3] = dgi[l][3][0] = d_be[l] * ia2 + be * d_ia2;
+        dgi[l][3][3] = -d_gpp[l] / (gpp * gpp) - 2.0 * be * d_be[l] * ia2 - be * be * d_ia2;
+        dgi[l][1][1] = -d_grr[l] / (grr * grr);
+        dgi[l][2][2] = -d_gtt[l] / (gtt * gtt);
+    }
+}
+
+/* Canonical right-hand side (eq. Ham) with the gridded metric:
+ * dx^mu = g^{mu nu} p_nu, dp_mu = -1/2 (d_mu g^{ab}) p_a p_b (mu = r, theta; the
+ * metric does not depend on t or phi). */
+static void grid_rhs(const grid_t *g, const double z[8], double f[8])
+{
+    double gi[4][4], dgi[2][4][4];
+    grid_inverse_metric(g, z[1], z[2], gi, dgi);
+    for (int mu = 0; mu < 4; ++mu) {
+        double acc = 0.0;
+        for (int nu = 0; nu < 4; ++nu) acc += gi[mu][nu] * z[4 + nu];
+        f[mu] = acc;
+    }
+    f[4] = 0.0;
+    f[7] = 0.0;
+    for (int l = 0; l < 2; ++l) {
+        double acc = 0.0;
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b) acc += dgi[l][a][b] * z[4 + a] * z[4 + b];
+        f[5 + l] = -0.5 * acc;
+    }
+}
+
+void oracle_grid_rhs(int64_t nr, int64_t nth, double r0, double dr, double th0, double dth,
+                     const double *nodes, const double *z, double *f)
+{
+    grid_t g = {nr, nth, r0, dr, th0, dth, nodes};
+    grid_rhs(&g, z, f);
+}
+
+/* Fixed-step RK4 on the gridded metric with the stop rules of the analytic path:
+ * stage radius <= r_stop -> HORIZON (start state kept); result non-finite, theta
+ * outside (0, pi), or a stage point or the result outside the grid's interior
+ * [r0 + dr, r0 + (nr - 2) dr] x [th0 + dth, th0 + (nth - 2) dth] -> NONFINITE (start
+ * state kept); then r <= r_stop -> HORIZON, r >= r_escape -> ESCAPE. */
+int oracle_integrate_grid(int64_t nr, int64_t nth, double r0, double dr, double th0, double dth,
+                          const double *nodes, int64_t n, double *state, int32_t *status,
+                          int32_t *steps, double h, int64_t n_steps, double r_stop,
+                          double r_escape, int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+    grid_t g = {nr, nth, r0, dr, th0, dth, nodes};
+    const double rlo = r0 + dr, rhi = r0 + (double)(nr - 2) * dr;
+    const double tlo = th0 + dth, thi = th0 + (double)(nth - 2) * dth;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double y[8];
+        get_state(state, n, i, y);
+        int64_t k;
+        for (k = 0; k < n_steps && status[i] == ST_ACTIVE; ++k) {
+            /* RK4 written out with the inside-the-grid check on every stage point */
+            double k1[8], k2[8], k3[8], k4[8], Y[8], y1[8];
+            int outside = 0, zone = 0;
+            grid_rhs(&g, y, k1);
+            for (int c = 0; c < 8; ++c) Y[c] = y[c] + 0.5 * h * k1[c];
+            zone |= Y[1] <= r_stop;
+            outside |= !(Y[1] >= rlo && Y[1] <= rhi && Y[2] >= tlo && Y[2] <= thi);
+            if (!zone && !outside) grid_rhs(&g, Y, k2);
+            for (int c = 0; c < 8 && !zone && !outside; ++c) Y[c] = y[c] + 0.5 * h * k2[c];
+            if (!zone && !outside) {
+                zone |= Y[1] <= r_stop;
+                outside |= !(Y[1] >= rlo && Y[1] <= rhi && Y[2] >= tlo && Y[2] <= thi);
+            }
+            if (!zone && !outside) grid_rhs(&g, Y, k3);
+            for (int c = 0; c < 8 && !zone && !outside; ++c) Y[c] = y[c] + h * k3[c];
+            if (!zone && !outside) {
+                zone |= Y[1] <= r_stop;
+                outside |= !(Y[1] >= rlo && Y[1] <= rhi && Y[2] >= tlo && Y[2] <= thi);
+            }
+            if (zone) { status[i] = ST_HORIZON; continue; }
+            if (outside) { status[i] = ST_NONFINITE; continue; }
+            grid_rhs(&g, Y, k4);
+            for (int c = 0; c < 8; ++c)
+                y1[c] = y[c] + h / 6.0 * (k1[c] + 2.0 * k2[c] + 2.0 * k3[c] + k4[c]);
+            if (!usable(y1) || !(y1[1] >= rlo && y1[1] <= rhi && y1[2] >= tlo && y1[2] <= thi)) {
+                status[i] = ST_NONFINITE;
+                continue;
+            }
+            memcpy(y, y1, sizeof y1);
+            if (y[1] <= r_stop) status[i] = ST_HORIZON;
+            else if (y[1] >= r_escape) status[i] = ST_ESCAPE;
+        }
+        steps[i] += (int32_t)k;
+        put_state(state, n, i, y);
+    }
+    return 0;
+}
+
+/* ================================================================================ */
 /* Camera: backward-traced null geodesics with a thin equatorial disk                */
 /* ================================================================================ */
 /* Image plane (Bardeen 1973) of a static observer at (r_obs, theta_obs = incl,

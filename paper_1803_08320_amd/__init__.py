@@ -24,6 +24,7 @@ __all__ = [
     "ICSpec", "Camera", "init_particles", "integrate", "invariants", "trace_camera",
     "workspace_bytes", "last_error", "version", "lib", "MalbecError", "STATUS", "adjoint",
     "IntegrateFromParams", "convert_state", "integrate_record", "integrate_adaptive",
+    "Grid", "grid_kerr", "integrate_grid",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -97,6 +98,12 @@ class c_adaptive(C.Structure):
                 ("steps_per_chunk", C.c_int32), ("pad_", C.c_int32)]
 
 
+class c_grid(C.Structure):
+    _fields_ = [("nr", C.c_int32), ("nth", C.c_int32), ("r0", C.c_double), ("dr", C.c_double),
+                ("th0", C.c_double), ("dth", C.c_double), ("r_stop", C.c_double),
+                ("nodes", C.c_void_p)]
+
+
 EXPORTS = {
     "malbec_last_error": (C.c_char_p, []),
     "malbec_version": (C.c_int, []),
@@ -114,6 +121,10 @@ EXPORTS = {
                                             C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                             C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
                                             C.c_void_p]),
+    "malbec_grid_fill_kerr": (C.c_int, [C.POINTER(c_grid), C.c_double, C.c_double, C.c_void_p,
+                                        C.c_void_p]),
+    "malbec_integrate_grid": (C.c_int, [C.POINTER(c_run), C.POINTER(c_grid), C.c_int64,
+                                        C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "malbec_integrate_record": (C.c_int, [C.POINTER(c_run), C.POINTER(c_batch), C.c_int64,
                                           C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                           C.c_void_p, C.c_void_p]),
@@ -312,6 +323,52 @@ def integrate_adaptive(state: torch.Tensor, tau: torch.Tensor, h: torch.Tensor,
                                            _ptr(rejects, torch.int32, n, "rejects"),
                                            _ptr(ws), ws.numel() if ws is not None else 0,
                                            _stream()))
+
+
+@dataclass
+class Grid:
+    """A 3+1 metric on a uniform (r, theta) grid (include/malbec.h, malbec_grid):
+    nodes is a device float64 tensor [nr, nth, 5] of (alpha, beta^phi, gamma_rr,
+    gamma_thth, gamma_phph / sin^2 theta)."""
+    nodes: torch.Tensor
+    r0: float
+    dr: float
+    th0: float
+    dth: float
+    r_stop: float
+
+    def to_c(self):
+        nr, nth, k = self.nodes.shape
+        if k != 5:
+            raise ValueError("nodes must have shape [nr, nth, 5]")
+        _ptr(self.nodes, torch.float64, nr * nth * 5, "nodes")
+        return c_grid(nr, nth, self.r0, self.dr, self.th0, self.dth, self.r_stop,
+                      self.nodes.data_ptr())
+
+
+def grid_kerr(M: float, a: float, nr: int, nth: int, r0: float, dr: float, th0: float, dth: float,
+              r_stop: float) -> Grid:
+    """A grid filled on the device with Kerr's 3+1 functions (Section 2)."""
+    g = Grid(torch.empty((nr, nth, 5), dtype=torch.float64, device="cuda"), r0, dr, th0, dth,
+             r_stop)
+    cg = g.to_c()
+    _check(lib().malbec_grid_fill_kerr(C.byref(cg), M, a, C.c_void_p(g.nodes.data_ptr()),
+                                       _stream()))
+    return g
+
+
+def integrate_grid(state: torch.Tensor, status: torch.Tensor, steps: torch.Tensor, grid: Grid,
+                   h: float, n_steps: int, r_escape: float, block: int = 0,
+                   steps_per_chunk: int = 0):
+    """Canonical RK4 of state[8, n] = (x, p) in the gridded 3+1 metric (in place)."""
+    n = state.shape[-1]
+    run = c_run(h, n_steps, F64, block, 1.0, r_escape, 1.0, steps_per_chunk, 0, 0,
+                FORM_HAMILTONIAN)
+    cg = grid.to_c()
+    _check(lib().malbec_integrate_grid(C.byref(run), C.byref(cg), n,
+                                       _ptr(state, torch.float64, 8 * n, "state"),
+                                       _ptr(status, torch.int32, n, "status"),
+                                       _ptr(steps, torch.int32, n, "steps"), _stream()))
 
 
 def integrate_record(state: torch.Tensor, status: torch.Tensor, steps: torch.Tensor, spacetimes,

@@ -298,6 +298,63 @@ int malbec_integrate_adaptive(const malbec_adaptive *ad, const malbec_batch *b, 
                            (hipStream_t)stream);
 }
 
+static int check_grid(const malbec_grid *g)
+{
+    if (!g) return fail(MALBEC_EINVAL, "grid is NULL");
+    if (g->nr < 4 || g->nth < 4) return fail(MALBEC_EINVAL, "the grid needs >= 4 nodes per axis");
+    if ((int64_t)g->nr * g->nth > ((int64_t)1 << 31))
+        return fail(MALBEC_EINVAL, "grid too large");
+    if (!g->nodes) return fail(MALBEC_EINVAL, "grid nodes are NULL");
+    if (!(g->dr > 0.0) || !(g->dth > 0.0) || !isfinite(g->r0) || !isfinite(g->dr) ||
+        !isfinite(g->th0) || !isfinite(g->dth))
+        return fail(MALBEC_EINVAL, "need finite r0, th0 and dr, dth > 0");
+    if (!(g->th0 > 0.0) || !(g->th0 + (double)(g->nth - 1) * g->dth < M_PI))
+        return fail(MALBEC_EINVAL, "the theta range must lie inside (0, pi)");
+    if (!(g->r0 > 0.0)) return fail(MALBEC_EINVAL, "r0 must be > 0");
+    if (!(g->r_stop >= g->r0 + g->dr)) return fail(MALBEC_EINVAL, "r_stop must be >= r0 + dr");
+    return MALBEC_OK;
+}
+
+int malbec_grid_fill_kerr(const malbec_grid *g, double M, double a, double *nodes, void *stream)
+{
+    clear_error();
+    int rc = check_grid(g);
+    if (rc) return rc;
+    if (nodes != g->nodes) return fail(MALBEC_EINVAL, "nodes must be g->nodes");
+    if (!(M > 0.0) || !(a >= 0.0) || !(a <= M)) return fail(MALBEC_EINVAL, "need M > 0 and 0 <= a <= M");
+    if (!(g->r0 > M + sqrt(M * M - a * a)))
+        return fail(MALBEC_EINVAL, "the grid must start outside the horizon");
+    return launch_grid_fill_kerr(*g, M, a, nodes, (hipStream_t)stream);
+}
+
+int malbec_integrate_grid(const malbec_run *run, const malbec_grid *g, int64_t n, double *state,
+                          int32_t *status, int32_t *steps, void *stream)
+{
+    clear_error();
+    if (!run) return fail(MALBEC_EINVAL, "run is NULL");
+    int rc = check_grid(g);
+    if (rc) return rc;
+    if (n < 0) return fail(MALBEC_EINVAL, "n = %lld < 0", (long long)n);
+    if (n > 0 && (!state || !status || !steps))
+        return fail(MALBEC_EINVAL, "state, status and steps must be non-NULL");
+    if (n > ((int64_t)1 << 40)) return fail(MALBEC_EINVAL, "n too large");
+    if (!(run->h > 0.0) || !isfinite(run->h)) return fail(MALBEC_EINVAL, "h = %g must be > 0", run->h);
+    if (run->n_steps < 0 || run->n_steps > INT32_MAX)
+        return fail(MALBEC_EINVAL, "n_steps = %lld outside [0, 2^31)", (long long)run->n_steps);
+    if (run->block < 0 || run->block > 1024 || (run->block % 64) != 0)
+        return fail(MALBEC_EINVAL, "block = %d must be a multiple of 64 in [64, 1024] or 0", run->block);
+    if (run->steps_per_chunk < 0) return fail(MALBEC_EINVAL, "steps_per_chunk < 0");
+    if (run->formulation != MALBEC_FORM_HAMILTONIAN)
+        return fail(MALBEC_EINVAL, "the gridded metric integrates (x, p): formulation must be HAMILTONIAN");
+    if (run->precision != MALBEC_F64) return fail(MALBEC_ENOTSUP, "the gridded metric is FP64 only");
+    if (run->persistent || run->checkpoint_every > 0)
+        return fail(MALBEC_ENOTSUP, "the gridded metric runs without persistent kernel or checkpoints");
+    if (!(run->r_escape > g->r_stop) || !(run->r_escape <= g->r0 + (double)(g->nr - 2) * g->dr))
+        return fail(MALBEC_EINVAL, "r_escape must lie inside the grid, above r_stop");
+    if (n == 0 || run->n_steps == 0) return MALBEC_OK;
+    return launch_integrate_grid(*run, *g, n, state, status, steps, (hipStream_t)stream);
+}
+
 int malbec_integrate_record(const malbec_run *run, const malbec_batch *b, int64_t n, double *state,
                             int32_t *status, int32_t *steps, int32_t record_every, double *traj,
                             void *stream)

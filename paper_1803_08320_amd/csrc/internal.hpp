@@ -66,6 +66,9 @@ int launch_convert(const StTable &T, const int32_t *st_of_lane, int64_t n, doubl
 int launch_adaptive(const malbec_adaptive &ad, const StTable &T, const int32_t *st_of_lane,
                     int64_t n, double *state, double *tau, double *h, int32_t *status,
                     int32_t *steps, int32_t *rejects, void *ws, hipStream_t s);
+int launch_grid_fill_kerr(const malbec_grid &g, double M, double a, double *nodes, hipStream_t s);
+int launch_integrate_grid(const malbec_run &run, const malbec_grid &g, int64_t n, double *state,
+                          int32_t *status, int32_t *steps, hipStream_t s);
 int launch_integrate_record(const malbec_run &run, const StTable &T, const int32_t *st_of_lane,
                             int64_t n, double *state, int32_t *status, int32_t *steps,
                             int32_t record_every, double *traj, hipStream_t s);

@@ -49,6 +49,7 @@ def test_struct_layout_matches_header(m, tmp_path):
                    "#define O(T, f) printf(#T \".\" #f \" %zu\\n\", offsetof(T, f));\n"
                    "int main(void){P(malbec_spacetime)P(malbec_batch)P(malbec_ic_spec)"
                    "P(malbec_run)P(malbec_camera)P(malbec_adaptive)O(malbec_adaptive, max_attempts)"
+                   "P(malbec_grid)O(malbec_grid, r_stop)O(malbec_grid, nodes)"
                    "O(malbec_adaptive, steps_per_chunk)O(malbec_ic_spec, rows)O(malbec_ic_spec, max_attempts)"
                    "O(malbec_run, checkpoint_every)O(malbec_run, persistent)O(malbec_run, formulation)"
                    "O(malbec_camera, max_steps)O(malbec_camera, persistent)"
@@ -63,6 +64,9 @@ def test_struct_layout_matches_header(m, tmp_path):
     assert int(got["malbec_run"]) == C.sizeof(m.c_run)
     assert int(got["malbec_camera"]) == C.sizeof(m.c_camera)
     assert int(got["malbec_adaptive"]) == C.sizeof(m.c_adaptive)
+    assert int(got["malbec_grid"]) == C.sizeof(m.c_grid)
+    assert int(got["malbec_grid.r_stop"]) == m.c_grid.r_stop.offset
+    assert int(got["malbec_grid.nodes"]) == m.c_grid.nodes.offset
     assert int(got["malbec_adaptive.max_attempts"]) == m.c_adaptive.max_attempts.offset
     assert int(got["malbec_adaptive.steps_per_chunk"]) == m.c_adaptive.steps_per_chunk.offset
     assert int(got["malbec_ic_spec.rows"]) == m.c_ic_spec.rows.offset
@@ -203,6 +207,27 @@ def test_adaptive_argument_errors(m, kw, expect):
                                            FAKE, FAKE, None, 0, None)
     assert rc == expect, m.last_error()
     assert m.workspace_bytes(m.OP_ADAPTIVE, 10, 1) >= 8
+
+
+@pytest.mark.parametrize("kw,run_kw,expect", [
+    (dict(nr=3), {}, -1), (dict(dr=0.0), {}, -1), (dict(th0=0.0), {}, -1),
+    (dict(dth=1.0), {}, -1), (dict(r_stop=1.0), {}, -1), (dict(nodes=None), {}, -1),
+    ({}, dict(formulation=0), -1), ({}, dict(precision=1), -4), ({}, dict(persistent=1), -4),
+    ({}, dict(r_escape=100.0), -1), ({}, dict(h=-1.0), -1),
+])
+def test_grid_argument_errors(m, kw, run_kw, expect):
+    d = dict(nr=16, nth=8, r0=2.5, dr=0.5, th0=0.5, dth=0.2, r_stop=3.2, nodes=0x1000)
+    d.update(kw)
+    g = m.c_grid(**d)
+    r = dict(formulation=1, r_escape=8.0)
+    r.update(run_kw)
+    run = _run(m, **r)
+    rc = m.lib().malbec_integrate_grid(C.byref(run), C.byref(g), 4, FAKE, FAKE, FAKE, None)
+    assert rc == expect, m.last_error()
+    d = dict(nr=16, nth=8, r0=2.5, dr=0.5, th0=0.5, dth=0.2, r_stop=3.2, nodes=0x1000)
+    g = m.c_grid(**d)
+    assert m.lib().malbec_grid_fill_kerr(C.byref(g), 1.0, 0.5, C.c_void_p(0x2000), None) == -1
+    assert m.lib().malbec_grid_fill_kerr(C.byref(g), 1.0, 1.5, C.c_void_p(0x1000), None) == -1
 
 
 def test_flop_count_constant(m, tmp_path):
