@@ -141,8 +141,8 @@ typedef struct {
     int32_t checkpoint_every;/* K > 0: write the state every K steps (see malbec_integrate) */
     int32_t persistent;      /* 1: persistent kernel refilling lanes that stop early from a
                                 work counter in ws (needs persistent = 0 for checkpoints) */
-    int32_t formulation;     /* MALBEC_FORM_*; HAMILTONIAN needs precision F64 and no
-                                checkpoints (MALBEC_ENOTSUP otherwise) */
+    int32_t formulation;     /* MALBEC_FORM_*; HAMILTONIAN runs with F64 or F32_KAHAN and
+                                without checkpoints (MALBEC_ENOTSUP otherwise) */
 } malbec_run;
 
 /* Adaptive integration controls (malbec_integrate_adaptive): Dormand-Prince 5(4)

@@ -151,8 +151,6 @@ int malbec_integrate(const malbec_run *run, const malbec_batch *b, int64_t n, do
     if (run->formulation != MALBEC_FORM_CHRISTOFFEL && run->formulation != MALBEC_FORM_HAMILTONIAN)
         return fail(MALBEC_EINVAL, "unknown formulation %d", run->formulation);
     if (run->formulation == MALBEC_FORM_HAMILTONIAN) {
-        if (run->precision != MALBEC_F64)
-            return fail(MALBEC_ENOTSUP, "the Hamiltonian formulation is FP64 only");
         if (run->checkpoint_every > 0)
             return fail(MALBEC_ENOTSUP, "checkpoints need the Christoffel formulation");
     }

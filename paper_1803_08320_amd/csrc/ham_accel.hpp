@@ -71,17 +71,17 @@ MALBEC_HD inline void kerr_ham(T M, T a, T r, T s, T c, T pr, T pth, const HamCo
     dpth = -fma(a2 * (s * c), twoH, hdthN) * irho2;
 }
 
-// One classic RK4 step (b = 1/6, 1/3, 1/3, 1/6; c = 0, 1/2, 1/2, 1) of the canonical
-// state z = (t, r, theta, phi, p_t, p_r, p_theta, p_phi).
+// Stages of one classic RK4 step (b = 1/6, 1/3, 1/3, 1/6; c = 0, 1/2, 1/2, 1) of the
+// canonical state z = (t, r, theta, phi, p_t, p_r, p_theta, p_phi).
 // f(stage, r, theta, p_r, p_theta, dt, dr, dth, dph, dpr, dpth) evaluates the
-// right-hand side at stage point `stage`; p_t and p_phi are copied unchanged.  sr[]
-// receives the radii of the three intermediate stage points.
+// right-hand side at stage point `stage`; acc[] receives the weighted sums
+// k1 + 2 k2 + 2 k3 + k4 of (t, r, theta, phi, p_r, p_theta) and sr[] the radii of the
+// three intermediate stage points.  p_t and p_phi do not change.
 template <typename T, typename F>
-MALBEC_HD inline void rk4_ham_step(F &f, T h, const T z[8], T z1[8], T sr[3])
+MALBEC_HD inline void rk4_ham_stages(F &f, T h, const T z[8], T acc[6], T sr[3])
 {
     const T hh = T(0.5) * h;
     T dt, dr, dth, dph, dpr, dpth;
-    T acc[6];  // weighted sums for (t, r, theta, phi, p_r, p_theta)
     T s1, s2, s3, s4;  // stage point (r, theta, p_r, p_theta)
 
     f(0, z[1], z[2], z[5], z[6], dt, dr, dth, dph, dpr, dpth);
@@ -103,7 +103,14 @@ MALBEC_HD inline void rk4_ham_step(F &f, T h, const T z[8], T z1[8], T sr[3])
 
     f(3, s1, s2, s3, s4, dt, dr, dth, dph, dpr, dpth);
     acc[0] += dt; acc[1] += dr; acc[2] += dth; acc[3] += dph; acc[4] += dpr; acc[5] += dpth;
+}
 
+// One RK4 step: z1 = z + h/6 (k1 + 2 k2 + 2 k3 + k4), p_t and p_phi copied.
+template <typename T, typename F>
+MALBEC_HD inline void rk4_ham_step(F &f, T h, const T z[8], T z1[8], T sr[3])
+{
+    T acc[6];
+    rk4_ham_stages(f, h, z, acc, sr);
     const T h6 = h * T(1.0 / 6.0);
     z1[0] = fma(h6, acc[0], z[0]);
     z1[1] = fma(h6, acc[1], z[1]);
@@ -113,6 +120,23 @@ MALBEC_HD inline void rk4_ham_step(F &f, T h, const T z[8], T z1[8], T sr[3])
     z1[5] = fma(h6, acc[4], z[5]);
     z1[6] = fma(h6, acc[5], z[6]);
     z1[7] = z[7];
+}
+
+// The increment d = z1 - z alone (compensated updates); d[4] = d[7] = 0.
+template <typename T, typename F>
+MALBEC_HD inline void rk4_ham_delta(F &f, T h, const T z[8], T d[8], T sr[3])
+{
+    T acc[6];
+    rk4_ham_stages(f, h, z, acc, sr);
+    const T h6 = h * T(1.0 / 6.0);
+    d[0] = h6 * acc[0];
+    d[1] = h6 * acc[1];
+    d[2] = h6 * acc[2];
+    d[3] = h6 * acc[3];
+    d[4] = T(0);
+    d[5] = h6 * acc[4];
+    d[6] = h6 * acc[5];
+    d[7] = T(0);
 }
 
 }  // namespace malbec

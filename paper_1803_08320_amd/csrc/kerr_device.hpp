@@ -60,12 +60,10 @@ __device__ __forceinline__ void rotate(double s0, double c0, double d, double &s
     c = fma(c0, cd, -s0 * sd);
 }
 
-// sin and cos of theta in (0, pi) (every accepted state has theta there): Cody-Waite
-// reduction x = theta - k pi/2, k = rint(theta / (pi/2)) in {0, 1, 2}, with pi/2 split
-// in two parts so that k * kPio2Hi is exact, then the Taylor series of sin x through
-// x^17 and cos x through x^18 on |x| <= pi/4 (truncation below 1e-19), then the
-// quadrant swap.
-__device__ __forceinline__ void sincos_0pi(double th, double &s, double &c)
+// Cody-Waite reduction x = theta - k pi/2, k = rint(theta / (pi/2)), with pi/2 split
+// in two parts so that k * kPio2Hi is exact (|k| < 2^20), then the Taylor series of
+// sin x through x^17 and cos x through x^18 on |x| <= pi/4 (truncation below 1e-19).
+__device__ __forceinline__ double sincos_reduce(double th, double &sx, double &cx)
 {
     constexpr double kPio2Hi = 1.5707963267341256e+00;  // 33 significant bits of pi/2
     constexpr double kPio2Lo = 6.0771005065061922e-11;  // pi/2 - kPio2Hi
@@ -80,7 +78,7 @@ __device__ __forceinline__ void sincos_0pi(double th, double &s, double &c)
     ps = fma3(x2, ps, -kF7);
     ps = fma3(x2, ps, kF5);
     ps = fma3(x2, ps, -kF3);
-    const double sx = fma(x * x2, ps, x);
+    sx = fma(x * x2, ps, x);
     double pc = fma3(x2, kF18, -kF16);
     pc = fma3(x2, pc, kF14);
     pc = fma3(x2, pc, -kF12);
@@ -89,16 +87,35 @@ __device__ __forceinline__ void sincos_0pi(double th, double &s, double &c)
     pc = fma3(x2, pc, kF6);
     pc = fma3(x2, pc, -kF4);
     pc = fma(x2, pc, kF2);
-    const double cx = fma(-x2, pc, 1.0);
-    // k = 0: (sx, cx); k = 1: (cx, -sx); k = 2: (-sx, -cx)
+    cx = fma(-x2, pc, 1.0);
+    return k;
+}
+
+// sin and cos of theta in (0, pi) (every accepted state has theta there): k is 0, 1
+// or 2, and the quadrant swap is k = 0: (sx, cx); 1: (cx, -sx); 2: (-sx, -cx).
+__device__ __forceinline__ void sincos_0pi(double th, double &s, double &c)
+{
+    double sx, cx;
+    const double k = sincos_reduce(th, sx, cx);
     s = k == 1.0 ? cx : (k == 0.0 ? sx : -sx);
     c = k == 1.0 ? -sx : (k == 0.0 ? cx : -cx);
 }
 
+// sin and cos of any moderate theta (|theta| < 1e6; stage points may leave (0, pi)):
+// the same reduction with the quadrant k taken modulo 4.
+__device__ __forceinline__ void sincos_any(double th, double &s, double &c)
+{
+    double sx, cx;
+    const int q = ((int)sincos_reduce(th, sx, cx)) & 3;  // k mod 4, negative k too
+    const double ss = (q & 1) ? cx : sx, cc = (q & 1) ? sx : cx;
+    s = (q & 2) ? -ss : ss;
+    c = ((q + 1) & 2) ? -cc : cc;
+}
+
 // sin and cos of the theta of RK4 stage `stage`.  Stage 0 evaluates them and keeps
 // (theta, sin, cos); the later stages of the same step, whose theta differs from the
-// stage-0 theta by an exactly computed small d, rotate that pair instead (the library
-// sincos if |d| > kRotMax, or if the step brings theta close to a pole, where the
+// stage-0 theta by an exactly computed small d, rotate that pair instead (a fresh
+// evaluation if |d| > kRotMax, or if the step brings theta close to a pole, where the
 // rotation's cancellation would cost relative accuracy in sin theta).
 struct StageTrig {
     double th0, s0, c0;
@@ -111,7 +128,7 @@ struct StageTrig {
             s0 = s;
             c0 = c;
         } else if (!(fabs(d) <= kRotMax && fabs(d) <= 0.5 * s0)) {
-            sincos(th, &s, &c);
+            sincos_any(th, s, c);
         } else {
             rotate(s0, c0, d, s, c);
         }

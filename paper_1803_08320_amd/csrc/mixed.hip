@@ -15,17 +15,13 @@ namespace malbec {
 
 namespace {
 
-// FP32 right-hand side.  Stage 0 takes the library sincosf; later stages rotate that
-// pair by the small angle difference (Taylor terms through d^5 / d^6, truncation
-// below 1e-10 for |d| <= 0.125, far under FP32 rounding).
-struct AccelF32 {
-    float M, a;
+// FP32 sin and cos of the stage theta.  Stage 0 takes the library sincosf; later
+// stages rotate that pair by the small angle difference (Taylor terms through d^5 /
+// d^6, truncation below 1e-10 for |d| <= 0.125, far under FP32 rounding).
+struct StageTrigF32 {
     float th0, s0, c0;
-    __device__ __forceinline__ void operator()(int stage, float r, float th, float ut, float ur,
-                                               float uth, float uph, float &at, float &ar,
-                                               float &ath, float &aph)
+    __device__ __forceinline__ void operator()(int stage, float th, float &s, float &c)
     {
-        float s, c;
         const float d = th - th0;
         if (stage == 0 || !(fabsf(d) <= 0.125f && fabsf(d) <= 0.5f * s0)) {
             sincosf(th, &s, &c);
@@ -37,7 +33,34 @@ struct AccelF32 {
             s = fmaf(s0, cd, c0 * sd);
             c = fmaf(c0, cd, -s0 * sd);
         }
+    }
+};
+
+// FP32 right-hand sides: the Christoffel form and Hamilton's equations.
+struct AccelF32 {
+    float M, a;
+    StageTrigF32 trig;
+    __device__ __forceinline__ void operator()(int stage, float r, float th, float ut, float ur,
+                                               float uth, float uph, float &at, float &ar,
+                                               float &ath, float &aph)
+    {
+        float s, c;
+        trig(stage, th, s, c);
         kerr_accel<float>(M, a, r, s, c, ut, ur, uth, uph, at, ar, ath, aph);
+    }
+};
+
+struct HamF32 {
+    float M, a;
+    const HamConst<float> &P;
+    StageTrigF32 trig;
+    __device__ __forceinline__ void operator()(int stage, float r, float th, float pr, float pth,
+                                               float &dt, float &dr, float &dth, float &dph,
+                                               float &dpr, float &dpth)
+    {
+        float s, c;
+        trig(stage, th, s, c);
+        kerr_ham<float>(M, a, r, s, c, pr, pth, P, dt, dr, dth, dph, dpr, dpth);
     }
 };
 
@@ -70,7 +93,10 @@ __device__ __forceinline__ void two_sum(float a, float b, float &s, float &e)
 }
 
 // One lane as a work item: load splits the double state, step advances one step
-// (FP64 inside the zone, FP32 + two-sum outside), store recombines hi + lo.
+// (FP64 inside the zone, FP32 + two-sum outside), store recombines hi + lo.  HAM:
+// the state is (x^mu, p_mu) and the step is that of Hamilton's equations; p_t and
+// p_phi never change (their increment is exactly 0, and the two-sum keeps hi + lo).
+template <bool HAM>
 struct MixProg {
     const MixArgs &A;
     const Spacetime *table;
@@ -79,6 +105,8 @@ struct MixProg {
     struct Lane {
         float hi[8], lo[8];
         Spacetime S;
+        HamConst<double> P64;
+        HamConst<float> P32;
         int32_t st, taken;
     };
     __device__ __forceinline__ bool load(int64_t i, Lane &L)
@@ -96,6 +124,10 @@ struct MixProg {
         L.S = table[sid];
 #pragma unroll
         for (int k = 0; k < 8; ++k) split(A.state[k * A.n + i], L.hi[k], L.lo[k]);
+        if (HAM) {
+            L.P64 = ham_const(L.S.a, (double)L.hi[4] + (double)L.lo[4], (double)L.hi[7] + (double)L.lo[7]);
+            L.P32 = ham_const((float)L.S.a, L.hi[4], L.hi[7]);
+        }
         L.taken = 0;
         return A.n_steps > 0;
     }
@@ -108,7 +140,10 @@ struct MixProg {
             double y[8], y1[8], sr[3];
 #pragma unroll
             for (int c = 0; c < 8; ++c) y[c] = (double)L.hi[c] + (double)L.lo[c];
-            rk4_step_f64(S, A.h, y, y1, sr);
+            if (HAM)
+                rk4_step_ham_f64(S, L.P64, A.h, y, y1, sr);
+            else
+                rk4_step_f64(S, A.h, y, y1, sr);
             bool accept;
             L.st = terminate_f64(S, A.r_escape, sr, y1, accept);
             if (accept) {
@@ -116,9 +151,14 @@ struct MixProg {
                 for (int c = 0; c < 8; ++c) split(y1[c], L.hi[c], L.lo[c]);
             }
         } else {
-            AccelF32 f32{(float)S.M, (float)S.a, 0.0f, 0.0f, 1.0f};
             float d[8], sr[3];
-            rk4_delta(f32, (float)A.h, L.hi, d, sr);
+            if (HAM) {
+                HamF32 f32{(float)S.M, (float)S.a, L.P32, {0.0f, 0.0f, 1.0f}};
+                rk4_ham_delta(f32, (float)A.h, L.hi, d, sr);
+            } else {
+                AccelF32 f32{(float)S.M, (float)S.a, {0.0f, 0.0f, 1.0f}};
+                rk4_delta(f32, (float)A.h, L.hi, d, sr);
+            }
             if ((double)sr[0] <= S.r_stop || (double)sr[1] <= S.r_stop || (double)sr[2] <= S.r_stop) {
                 L.st = kHorizon;
             } else {
@@ -152,7 +192,7 @@ struct MixProg {
     }
 };
 
-template <bool MULTI>
+template <bool MULTI, bool HAM>
 __global__ void __launch_bounds__(256) rk4_f32k_kernel(MixArgs A, StTable T)
 {
     __shared__ Spacetime lds_st[kMaxSt];
@@ -160,15 +200,15 @@ __global__ void __launch_bounds__(256) rk4_f32k_kernel(MixArgs A, StTable T)
     __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= A.n) return;
-    MixProg P{A, lds_st, MULTI, T.n_st};
-    MixProg::Lane L;
+    MixProg<HAM> P{A, lds_st, MULTI, T.n_st};
+    typename MixProg<HAM>::Lane L;
     if (!P.load(i, L)) return;
     while (!P.step(L)) {
     }
     P.store(i, L);
 }
 
-template <bool MULTI>
+template <bool MULTI, bool HAM>
 __global__ void __launch_bounds__(256) rk4_f32k_persistent_kernel(MixArgs A, StTable T,
                                                                   unsigned long long *counter,
                                                                   int32_t chunk)
@@ -176,11 +216,33 @@ __global__ void __launch_bounds__(256) rk4_f32k_persistent_kernel(MixArgs A, StT
     __shared__ Spacetime lds_st[kMaxSt];
     for (int k = threadIdx.x; k < T.n_st; k += blockDim.x) lds_st[k] = T.st[k];
     __syncthreads();
-    MixProg P{A, lds_st, MULTI, T.n_st};
+    MixProg<HAM> P{A, lds_st, MULTI, T.n_st};
     persistent_loop(P, A.n, counter, chunk);
 }
 
 }  // namespace
+
+template <bool MULTI, bool HAM>
+int launch_f32k(const MixArgs &A, const StTable &T, bool persistent, int32_t sub, int block,
+                void *ws, hipStream_t s)
+{
+    if (persistent) {
+        int grid = 0;
+        int rc = persistent_grid((const void *)rk4_f32k_persistent_kernel<MULTI, HAM>, block, A.n, grid);
+        if (rc) return rc;
+        unsigned long long *counter = (unsigned long long *)ws;
+        hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(1), 0, s, counter);
+        MALBEC_LAUNCH_CHECK("zero_u64_kernel");
+        hipLaunchKernelGGL((rk4_f32k_persistent_kernel<MULTI, HAM>), dim3(grid), dim3(block), 0, s,
+                           A, T, counter, sub);
+        MALBEC_LAUNCH_CHECK("rk4_f32k_persistent_kernel");
+        return MALBEC_OK;
+    }
+    hipLaunchKernelGGL((rk4_f32k_kernel<MULTI, HAM>), dim3(grid_for(A.n, block)), dim3(block), 0, s,
+                       A, T);
+    MALBEC_LAUNCH_CHECK("rk4_f32k_kernel");
+    return MALBEC_OK;
+}
 
 int launch_integrate_f32k(const malbec_run &run, const StTable &T, const int32_t *st_of_lane,
                           int64_t n, double *state, int32_t *status, int32_t *steps, void *ws,
@@ -189,6 +251,7 @@ int launch_integrate_f32k(const malbec_run &run, const StTable &T, const int32_t
     const int block = run.block > 0 ? run.block : 256;
     if (block > 256) return fail(MALBEC_EINVAL, "block %d exceeds the kernel's launch bound 256", block);
     const bool multi = st_of_lane != nullptr && T.n_st > 1;
+    const bool ham = run.formulation == MALBEC_FORM_HAMILTONIAN;
     const int64_t total = run.n_steps;
     MixArgs A;
     A.n = n;
@@ -198,34 +261,22 @@ int launch_integrate_f32k(const malbec_run &run, const StTable &T, const int32_t
     A.st_of_lane = multi ? st_of_lane : nullptr;
     A.h = run.h;
     A.r_escape = run.r_escape;
+    auto go = [&](bool persistent, int32_t sub) {
+        if (multi)
+            return ham ? launch_f32k<true, true>(A, T, persistent, sub, block, ws, s)
+                       : launch_f32k<true, false>(A, T, persistent, sub, block, ws, s);
+        return ham ? launch_f32k<false, true>(A, T, persistent, sub, block, ws, s)
+                   : launch_f32k<false, false>(A, T, persistent, sub, block, ws, s);
+    };
     if (run.persistent) {
         A.n_steps = (int32_t)total;
-        const int32_t sub = run.steps_per_chunk > 0 ? run.steps_per_chunk : 64;
-        int grid = 0;
-        int rc = persistent_grid(multi ? (const void *)rk4_f32k_persistent_kernel<true>
-                                       : (const void *)rk4_f32k_persistent_kernel<false>,
-                                 block, n, grid);
-        if (rc) return rc;
-        unsigned long long *counter = (unsigned long long *)ws;
-        hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(1), 0, s, counter);
-        MALBEC_LAUNCH_CHECK("zero_u64_kernel");
-        if (multi)
-            hipLaunchKernelGGL((rk4_f32k_persistent_kernel<true>), dim3(grid), dim3(block), 0, s, A, T,
-                               counter, sub);
-        else
-            hipLaunchKernelGGL((rk4_f32k_persistent_kernel<false>), dim3(grid), dim3(block), 0, s, A,
-                               T, counter, sub);
-        MALBEC_LAUNCH_CHECK("rk4_f32k_persistent_kernel");
-        return MALBEC_OK;
+        return go(true, run.steps_per_chunk > 0 ? run.steps_per_chunk : 64);
     }
     const int64_t chunk = run.steps_per_chunk > 0 ? run.steps_per_chunk : total;
     for (int64_t k0 = 0; k0 < total; k0 += chunk) {
         A.n_steps = (int32_t)((total - k0) < chunk ? (total - k0) : chunk);
-        if (multi)
-            hipLaunchKernelGGL((rk4_f32k_kernel<true>), dim3(grid_for(n, block)), dim3(block), 0, s, A, T);
-        else
-            hipLaunchKernelGGL((rk4_f32k_kernel<false>), dim3(grid_for(n, block)), dim3(block), 0, s, A, T);
-        MALBEC_LAUNCH_CHECK("rk4_f32k_kernel");
+        int rc = go(false, 0);
+        if (rc) return rc;
     }
     return MALBEC_OK;
 }

@@ -110,7 +110,6 @@ FAKE = C.c_void_p(0x1000)  # never dereferenced: every case below fails validati
     (dict(persistent=2), ((1.0, 0.9),), 4, -1),
     (dict(persistent=1), ((1.0, 0.9),), 4, -2),        # persistent needs a workspace
     (dict(formulation=2), ((1.0, 0.9),), 4, -1),
-    (dict(formulation=1, precision=1), ((1.0, 0.9),), 4, -4),  # Hamiltonian is FP64 only
 ])
 def test_integrate_argument_errors(m, kw, sts, n, expect):
     run = _run(m, **kw)
@@ -118,6 +117,13 @@ def test_integrate_argument_errors(m, kw, sts, n, expect):
     rc = m.lib().malbec_integrate(C.byref(run), C.byref(b), n, FAKE, FAKE, FAKE, None, None, 0, None)
     assert rc == expect
     assert m.last_error() != ""
+
+
+def test_hamiltonian_with_checkpoints_is_unsupported(m):
+    run = _run(m, formulation=1, checkpoint_every=4)
+    arr, b = _batch(m)
+    rc = m.lib().malbec_integrate(C.byref(run), C.byref(b), 4, FAKE, FAKE, FAKE, FAKE, None, 0, None)
+    assert rc == -4 and "Christoffel" in m.last_error()
 
 
 def test_null_pointer_and_table_errors(m):

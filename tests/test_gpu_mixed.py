@@ -138,3 +138,82 @@ def test_persistent_equals_plain_bitwise(m, orc, precision, chunk):
     for x, y in zip(a, b):
         assert np.array_equal(x, y)
     assert b[1][7] == 2 and b[2][7] == 0 and np.array_equal(b[0][:, 7], s0[:, 7])
+
+
+def lower(orc, sts, s, st_of_lane=None):
+    z = s.copy()
+    for i in range(s.shape[1]):
+        M, a = sts[0 if st_of_lane is None else st_of_lane[i]]
+        z[4:, i] = orc.metric(M, a, s[1, i], s[2, i]) @ s[4:, i]
+    return z
+
+
+def test_hamiltonian_all_fp64_zone_reproduces_fp64(m, orc):
+    """Hamilton's equations (Section 2, eq. Ham) on the FP32-compensated state, every
+    step in the FP64 zone: parity with the oracle's canonical RK4."""
+    st = [(1.0, 0.9)]
+    rc, s0, _, _ = orc.ic_constants(23, st, 1000 + 11, KERR_RANGES)
+    z0 = lower(orc, st, s0)
+    got = run(m, st, z0, 0.02, 1500, precision="f32k", fp64_zone_factor=1e9,
+              formulation="hamiltonian")
+    ref = orc.integrate(st, z0, 0.02, 1500, hamiltonian=True)
+    compare(orc, st, z0, *got, *ref, lambda p0: orc.integrate(st, p0, 0.02, 1500, hamiltonian=True))
+
+
+def test_hamiltonian_mixed_batch_accuracy(m, orc):
+    """16 spins, FP32 compensated canonical state, FP64 within 1.2 r_+, 20,000 steps:
+    E = -p_t and L_z = p_phi stay exact, Q and the position within the stated
+    accuracy of the FP32-compensated path."""
+    per = 48
+    n = 16 * per
+    st_of_lane = np.repeat(np.arange(16), per).astype(np.int32)
+    rc, s0, c0, _ = orc.ic_constants(4, SPINS, n, KERR_RANGES, st_of_lane=st_of_lane)
+    z0 = lower(orc, SPINS, s0, st_of_lane)
+    n_steps = 20000
+    got = run(m, SPINS, z0, 0.02, n_steps, st_of_lane=st_of_lane, precision="f32k",
+              fp64_zone_factor=1.2, formulation="hamiltonian")
+    ref = orc.integrate(SPINS, z0, 0.02, n_steps, st_of_lane=st_of_lane, hamiltonian=True)
+    assert np.array_equal(got[1] == 1, ref[1] == 1)
+    assert np.all(np.abs(got[2][ref[1] == 1] - ref[2][ref[1] == 1]) <= 3)
+    # p_t, p_phi: the hi + lo split of the double (about 48 bits), never updated
+    assert np.all(np.abs(got[0][4] - z0[4]) <= 1e-14 * np.abs(z0[4]))
+    assert np.all(np.abs(got[0][7] - z0[7]) <= 1e-14 * np.abs(z0[7]))
+    both = (got[1] == 0) & (ref[1] == 0)
+    ug = np.stack([orc.inverse_metric(*SPINS[st_of_lane[i]], got[0][1, i], got[0][2, i]) @ got[0][4:, i]
+                   for i in range(n)], axis=1)
+    yg = np.concatenate([got[0][:4], ug])
+    inv_g = orc.invariants(SPINS, yg, st_of_lane=st_of_lane)
+    qok = both & (c0[2] >= 0.1)
+    dQ = np.abs(inv_g[2] / c0[2] - 1)[qok]
+    a_lane = np.array([SPINS[k][1] for k in st_of_lane])
+    pos = position_error(a_lane[both], got[0][:, both], ref[0][:, both])
+    stats = dict(dQ_p99=np.quantile(dQ, 0.99), pos_p99=np.quantile(pos, 0.99))
+    print("f32k Hamiltonian accuracy vs fp64 oracle:", {k: "%.2e" % v for k, v in stats.items()})
+    assert stats["dQ_p99"] < 1e-4
+    assert stats["pos_p99"] < 1e-2
+
+
+@pytest.mark.parametrize("chunk", [1, 64])
+def test_hamiltonian_f32k_persistent_equals_plain(m, orc, chunk):
+    import torch
+    per = 200
+    n = 16 * per
+    st_of_lane = np.repeat(np.arange(16), per).astype(np.int32)
+    rc, s0, _, _ = orc.ic_constants(5, SPINS, n, KERR_RANGES, st_of_lane=st_of_lane)
+    z0 = lower(orc, SPINS, s0, st_of_lane)
+    sol = torch.as_tensor(st_of_lane).cuda()
+
+    def go(persistent):
+        state = torch.as_tensor(np.ascontiguousarray(z0)).cuda()
+        stt = torch.zeros(n, dtype=torch.int32, device="cuda")
+        spp = torch.zeros(n, dtype=torch.int32, device="cuda")
+        m.integrate(state, stt, spp, SPINS, h=0.02, n_steps=3000, persistent=persistent,
+                    steps_per_chunk=chunk if persistent else 0, st_of_lane=sol, precision="f32k",
+                    fp64_zone_factor=1.2, formulation="hamiltonian")
+        torch.cuda.synchronize()
+        return state.cpu().numpy(), stt.cpu().numpy(), spp.cpu().numpy()
+
+    a, b = go(False), go(True)
+    assert (a[1] == 1).sum() > 100
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
