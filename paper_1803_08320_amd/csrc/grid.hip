@@ -149,7 +149,10 @@ __device__ __forceinline__ bool inside(const GridArgs &A, double r, double th)
     return r >= A.rlo && r <= A.rhi && th >= A.tlo && th <= A.thi;
 }
 
-__global__ void __launch_bounds__(256) rk4_grid_kernel(GridArgs A)
+// Two waves per SIMD: left alone the compiler spills a few values to AGPRs past 256
+// registers, which leaves one wave per SIMD to hide the gathers' latency.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8)))
+rk4_grid_kernel(GridArgs A)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= A.n) return;
