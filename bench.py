@@ -61,7 +61,7 @@ def measured_traffic_bytes():
 def parse():
     p = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=3)
+    p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--lanes", type=int, default=1 << 20)
     p.add_argument("--rk-steps", type=int, default=20000)
@@ -74,6 +74,8 @@ def parse():
     p.add_argument("--no-traj", action="store_true", help="skip the trajectory-output leg")
     p.add_argument("--no-adaptive", action="store_true", help="skip the adaptive (DP45) leg")
     p.add_argument("--no-grid", action="store_true", help="skip the gridded 3+1 metric leg")
+    p.add_argument("--no-e2e", action="store_true",
+                   help="skip the transfer-inclusive leg and the 1/8-shard leg")
     p.add_argument("--no-extra", action="store_true",
                    help="skip the camera, mixed-spin batch and adjoint legs")
     p.add_argument("--probe-copy-bytes", type=int, default=0,
@@ -175,7 +177,9 @@ def main():
                      "traffic": measured_traffic_bytes(), "kernel": "rk4_f64_kernel",
                      "algorithmic_bytes": 144.0 * n,
                      "flops_per_lane_step": m.FLOPS_PER_STEP_F64,
-                     "kernel_ms_avg": 1e3 * avg_kern_s},
+                     "kernel_ms_avg": 1e3 * avg_kern_s,
+                     "kernel_ms_median": float(np.median(kern_ms)),
+                     "kernel_ms_each": [round(x, 3) for x in kern_ms]},
         "physics": {"active_frac": float(act.mean()),
                     "dE_over_E_p99": float(np.quantile(dE, 0.99)) if dE.size else None,
                     "dQ_over_Q_p99": float(np.quantile(dQ, 0.99)) if dQ.size else None,
@@ -183,6 +187,71 @@ def main():
         "context": {"paper_gpu_lane_steps_per_s": 3.69e6,
                     "paper_hardware": "GTX 960M, Kerr a=0.5, h=0.1, FP64, no I/O"},
     }
+
+    if not args.no_e2e:
+        # the same workload with the state starting and ending in pinned host memory:
+        # host-to-device copy of the initial state, the integration and the
+        # device-to-host copy of state, status and steps, all inside the timed region
+        # (the figure a caller that hands over host buffers sees; not the headline)
+        res_final = state.clone()
+        host_in = s0.cpu().pin_memory()
+        host_out = torch.empty_like(host_in, device="cpu").pin_memory()
+        st_out = torch.empty(n, dtype=torch.int32).pin_memory()
+        sp_out = torch.empty(n, dtype=torch.int32).pin_memory()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+
+        def run_e2e():
+            ev[0].record()
+            state.copy_(host_in, non_blocking=True)
+            status.zero_()
+            steps.zero_()
+            ev[1].record()
+            m.integrate(state, status, steps, st, h=h, n_steps=n_rk, block=args.block)
+            ev[2].record()
+            host_out.copy_(state, non_blocking=True)
+            st_out.copy_(status, non_blocking=True)
+            sp_out.copy_(steps, non_blocking=True)
+            ev[3].record()
+        run_e2e()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        run_e2e()
+        torch.cuda.synchronize()
+        wall_e2e = time.perf_counter() - t
+        e_steps = int(sp_out.to(torch.int64).sum().item())
+        h2d_ms, d2h_ms = ev[0].elapsed_time(ev[1]), ev[2].elapsed_time(ev[3])
+        moved = 64.0 * n + 72.0 * n
+        result["end_to_end"] = {
+            "value": e_steps / wall_e2e, "unit": "lane-steps/s",
+            "vs_resident": e_steps / wall_e2e / result["value"],
+            "h2d_ms": h2d_ms, "d2h_ms": d2h_ms,
+            "pcie_GB_per_s": moved / ((h2d_ms + d2h_ms) / 1e3) / 1e9,
+            "bytes_moved": moved,
+            "bitwise_equal_to_resident": bool(torch.equal(host_out, res_final.cpu()))}
+
+        # one GPU's share of the same batch on eight GPUs (lane ranges of 131,072)
+        ns = n // 8
+        sh_state = s0[:, :ns].contiguous()
+        sh0 = sh_state.clone()
+        sh_status, sh_steps = m.new_lane_arrays(ns)
+        evs8 = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+        for rec in (False, True):
+            sh_state.copy_(sh0)
+            sh_status.zero_()
+            sh_steps.zero_()
+            if rec:
+                evs8[0].record()
+            m.integrate(sh_state, sh_status, sh_steps, st, h=h, n_steps=n_rk, block=args.block)
+            if rec:
+                evs8[1].record()
+        torch.cuda.synchronize()
+        dt8 = evs8[0].elapsed_time(evs8[1]) / 1e3
+        s8 = int(sh_steps.to(torch.int64).sum().item())
+        result["shard_1_of_8"] = {
+            "value": s8 / dt8, "unit": "lane-steps/s", "lanes": ns, "kernel_ms": 1e3 * dt8,
+            "vs_full_batch": s8 / dt8 / (per_step_lane_steps / avg_kern_s),
+            "bitwise_equal_to_full_batch_slice": bool(torch.equal(sh_state, res_final[:, :ns]))}
+        del sh_state, sh0, sh_status, sh_steps, res_final
 
     if not args.no_f32k:
         # FP32 state with compensated update, FP64 within 1.2 r_+: same ICs, one timed run

@@ -120,3 +120,38 @@ def test_gridded_kerr_tracks_analytic_kerr(m, orc):
     both = (got[1] == 0) & (status.cpu().numpy() == 0)
     assert both.mean() > 0.95
     assert mixed_rel(got[0][:, both], ana[:, both]).max() < 1e-4
+
+
+def test_grid_full_size_sampled(m, orc):
+    """The benchmark's gridded launch: 1,048,576 Kerr a = 0.9 lanes x 2,000 steps on
+    an 801 x 401 grid filled on the device (all nodes checked against the oracle's
+    fill); 256 strided lanes hold the oracle's initial data and are compared with the
+    oracle's integration on its own grid."""
+    import torch
+    from parity import mixed_rel
+    st = [(1.0, 0.9)]
+    n = 1 << 20
+    geo = (1.0, 0.9, 801, 401, 1.5, 60.0 / 800, 0.1, (math.pi - 0.2) / 400)
+    r_stop = 1.2 * r_plus(0.9)
+    g = m.grid_kerr(*geo, r_stop)
+    G = orc.grid_kerr(*geo)
+    got_nodes = g.nodes.cpu().numpy()
+    assert np.max(np.abs(got_nodes - G.nodes) / (np.abs(G.nodes) + 1.0)) < 1e-14
+    del got_nodes
+    spec = m.ICSpec(mode=m.IC_CONSTANTS, seed=2, r_range=KERR_RANGES[0], th_range=KERR_RANGES[1],
+                    E_range=KERR_RANGES[2], Lz_range=KERR_RANGES[3], Q_range=KERR_RANGES[4])
+    state, _, _ = m.init_particles(spec, st, n)
+    m.convert_state(state, st, True)
+    idx = np.arange(0, n, n // 256)
+    s0 = np.concatenate([orc.ic_constants(2, st, 1, KERR_RANGES, lane0=int(i))[1] for i in idx], axis=1)
+    z0 = lower(orc, st, s0)
+    assert mixed_rel(state.cpu().numpy()[:, idx], z0).max() < 5e-13
+    state[:, torch.as_tensor(idx, device="cuda")] = to_dev(z0, torch.float64)
+    status, steps = m.new_lane_arrays(n)
+    m.integrate_grid(state, status, steps, g, 0.02, 2000, 55.0)
+    torch.cuda.synchronize()
+    got = (state.cpu().numpy()[:, idx], status.cpu().numpy()[idx], steps.cpu().numpy()[idx])
+    ref = orc.integrate_grid(G, z0, 0.02, 2000, r_stop=r_stop, r_escape=55.0)
+    compare(orc, st, z0, *got, *ref,
+            lambda p0: orc.integrate_grid(G, p0, 0.02, 2000, r_stop=r_stop, r_escape=55.0))
+    assert (status == 0).float().mean().item() > 0.99

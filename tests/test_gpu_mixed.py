@@ -217,3 +217,60 @@ def test_hamiltonian_f32k_persistent_equals_plain(m, orc, chunk):
     assert (a[1] == 1).sum() > 100
     for x, y in zip(a, b):
         assert np.array_equal(x, y)
+
+
+def test_mixed_full_size_sampled(m, orc):
+    """The benchmark's mixed-spin launches: 16 spins x 262,144 contiguous lanes
+    (4,194,304), 20,000 steps, persistent queue.  16 strided lanes per spin hold the
+    oracle's initial data.  FP64: parity with the oracle on those lanes.  FP32
+    compensated: the accuracy bounds of the reduced test, on the same lanes."""
+    import torch
+    per = 262144
+    n = 16 * per
+    sol_h = np.repeat(np.arange(16), per).astype(np.int32)
+    sol = torch.as_tensor(sol_h).cuda()
+    s_dev, c_dev, _ = m.init_particles(m.ICSpec(mode=m.IC_CONSTANTS, seed=4), SPINS, n, st_of_lane=sol)
+    idx = np.concatenate([k * per + np.arange(0, per, per // 16) for k in range(16)])
+    spin = sol_h[idx]
+    s0 = np.concatenate([orc.ic_constants(4, SPINS, 1, KERR_RANGES, st_of_lane=spin[j:j + 1],
+                                          lane0=int(i))[1] for j, i in enumerate(idx)], axis=1)
+    assert mixed_rel(s_dev.cpu().numpy()[:, idx], s0).max() < 5e-13
+    s_dev[:, torch.as_tensor(idx, device="cuda")] = torch.as_tensor(s0).cuda()
+    c0 = orc.invariants(SPINS, s0, st_of_lane=spin)
+    ref = orc.integrate(SPINS, s0, 0.02, 20000, st_of_lane=spin)
+    state = torch.empty_like(s_dev)
+    status, steps = m.new_lane_arrays(n)
+    out = {}
+    for prec in ("f64", "f32k"):
+        state.copy_(s_dev)
+        status.zero_()
+        steps.zero_()
+        m.integrate(state, status, steps, SPINS, h=0.02, n_steps=20000, st_of_lane=sol,
+                    precision=prec, fp64_zone_factor=1.2, persistent=True)
+        torch.cuda.synchronize()
+        out[prec] = (state.cpu().numpy()[:, idx], status.cpu().numpy()[idx], steps.cpu().numpy()[idx])
+    del state, s_dev
+    for k in range(16):
+        sel = spin == k
+        got = tuple(x[..., sel] for x in out["f64"])
+        compare(orc, [SPINS[k]], s0[:, sel], *got, ref[0][:, sel], ref[1][sel], ref[2][sel],
+                lambda p0, k=k: orc.integrate([SPINS[k]], p0, 0.02, 20000))
+    got = out["f32k"]
+    plunge = ref[1] == 1
+    assert plunge.sum() > 10
+    # a near-critical lane may stop a step earlier or later, or on the other side of
+    # the horizon test, under the ~1e-7 relative FP32 rounding
+    assert np.sum((got[1] == 1) != plunge) <= 1
+    both_pl = plunge & (got[1] == 1)
+    assert np.all(np.abs(got[2][both_pl] - ref[2][both_pl]) <= 3)
+    both = (got[1] == 0) & (ref[1] == 0)
+    inv_g = orc.invariants(SPINS, got[0], st_of_lane=spin)
+    dE = np.abs(inv_g[0] / c0[0] - 1)[both]
+    dQ = np.abs(inv_g[2] / c0[2] - 1)[both & (c0[2] >= 0.1)]
+    a_lane = np.array([SPINS[k][1] for k in spin])
+    pos = position_error(a_lane[both], got[0][:, both], ref[0][:, both])
+    print("f32k full size vs fp64 oracle: dE p99 %.2e dQ p99 %.2e pos p99 %.2e"
+          % (np.quantile(dE, 0.99), np.quantile(dQ, 0.99), np.quantile(pos, 0.99)))
+    assert np.quantile(dE, 0.99) < 1e-5
+    assert np.quantile(dQ, 0.99) < 1e-4
+    assert np.quantile(pos, 0.99) < 1e-2

@@ -153,3 +153,37 @@ def test_streaming_driver_is_the_direct_call(m, orc, tmp_path):
     stream_trajectories(state, status, steps, st, 0.02, 1000, 10, 32, sink)
     sink.close()
     assert np.array_equal(np.fromfile(path, dtype=np.float64).reshape(100, 5, n), direct)
+
+
+def test_stream_full_size_sampled(m, orc):
+    """The benchmark's output launch: 1,048,576 Kerr a = 0.9 lanes x 20,000 steps, a
+    record every 200 steps, 10 records per chunk through the double-buffered
+    streaming driver; the records of 256 strided lanes (holding the oracle's initial
+    data) against the oracle's states converted by eq. coord."""
+    import torch
+    from paper_1803_08320_amd.stream import stream_trajectories
+    st = [(1.0, 0.9)]
+    n = 1 << 20
+    spec = m.ICSpec(mode=m.IC_CONSTANTS, seed=2, r_range=KERR_RANGES[0], th_range=KERR_RANGES[1],
+                    E_range=KERR_RANGES[2], Lz_range=KERR_RANGES[3], Q_range=KERR_RANGES[4])
+    state, _, _ = m.init_particles(spec, st, n)
+    idx = np.arange(0, n, n // 256)
+    s0 = np.concatenate([orc.ic_constants(2, st, 1, KERR_RANGES, lane0=int(i))[1] for i in idx], axis=1)
+    assert mixed_rel(state.cpu().numpy()[:, idx], s0).max() < 5e-13
+    state[:, torch.as_tensor(idx, device="cuda")] = to_dev(s0, torch.float64)
+    status, steps = m.new_lane_arrays(n)
+    kept = {}
+
+    def sink(recs, k):
+        kept[k] = recs[:, :, idx].copy()
+    info = stream_trajectories(state, status, steps, st, 0.02, 20000, 200, 10, sink)
+    torch.cuda.synchronize()
+    assert info["records"] == 100 and sorted(kept) == list(range(10))
+    traj = np.concatenate([kept[k] for k in range(10)])
+    got = (state.cpu().numpy()[:, idx], status.cpu().numpy()[idx], steps.cpu().numpy()[idx])
+    ref_traj, ref = oracle_records(orc, st, s0, 0.02, 20000, 200)
+    compare(orc, st, s0, *got, *ref, lambda p0: orc.integrate(st, p0, 0.02, 20000))
+    good = (mixed_rel(got[0], ref[0]) <= 1e-10) & (got[1] == ref[1]) & (got[2] == ref[2])
+    assert good.mean() > 0.98
+    err = np.abs(traj - ref_traj) / (np.abs(ref_traj) + 1.0)
+    assert err[:, :, good].max() <= 1e-10
