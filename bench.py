@@ -490,8 +490,15 @@ def main():
         t = time.perf_counter()
         _, _, ref_steps = oracle.integrate(st, sc, h, n_rk, nthreads=nthreads)
         dt = time.perf_counter() - t
+        cpu_model = None
+        try:
+            with open("/proc/cpuinfo") as fh:
+                cpu_model = next((ln.split(":", 1)[1].strip() for ln in fh
+                                  if ln.startswith("model name")), None)
+        except OSError:
+            pass
         result["cpu_baseline"] = {"value": float(ref_steps.sum()) / dt, "unit": "lane-steps/s",
-                                  "cores": nthreads, "kind": "oracle",
+                                  "cores": nthreads, "kind": "oracle", "cpu_model": cpu_model,
                                   "sample": "%d strided lanes of the workload x %d RK4 steps "
                                             "(%.1f s wall)" % (len(idx), n_rk, dt)}
     print(json.dumps(result))
@@ -548,6 +555,27 @@ def extra_legs(m, torch, np):
         out[name] = {"lane_steps_per_s": ls / dt, "ms": 1e3 * dt,
                      "plunged_frac": float((status == 1).float().mean().item())}
         if name == "mixed_f32k_persistent":
+            # the same launch with the FP64 invariant monitor folded into the step loop
+            # every 1,000 steps
+            mon = torch.empty((8, n), dtype=torch.float64, device="cuda")
+
+            def run_mon():
+                state.copy_(s0)
+                status.zero_()
+                steps.zero_()
+                m.integrate_monitored(state, status, steps, spins, 0.02, 20000, 1000, monitor=mon,
+                                      st_of_lane=sol, precision="f32k", fp64_zone_factor=1.2,
+                                      persistent=True)
+            dtm = _timed(torch, run_mon)
+            lsm = int(steps.sum().item())
+            act_m = status == 0
+            rel = (mon[4:] / mon[:4].abs().clamp_min(1e-300))
+            q_ok_m = act_m & (mon[2] >= 0.1)
+            out["mixed_f32k_persistent_monitored"] = {
+                "lane_steps_per_s": lsm / dtm, "ms": 1e3 * dtm, "monitor_every": 1000,
+                "max_dE_over_E_p99": float(torch.quantile(rel[0][act_m][:1 << 20], 0.99).item()),
+                "max_dQ_over_Q_p99": float(torch.quantile(rel[2][q_ok_m][:1 << 20], 0.99).item())}
+            # the monitored run leaves state, status and steps bitwise as the plain one
             m.invariants(state, spins, st_of_lane=sol, out=inv)
             act = (status == 0)
             q_ok = act & (c0[2] >= 0.1)

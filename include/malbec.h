@@ -240,6 +240,31 @@ MALBEC_API int malbec_integrate(const malbec_run *run, const malbec_batch *b, in
                      int32_t *status, int32_t *steps, double *checkpoints, void *ws,
                      size_t ws_bytes, void *stream);
 
+/* malbec_integrate with the invariant monitor inside the step loop.  The conserved
+ * quantities of Kerr geodesics, E = -p_t and L_z = p_phi (Sections 3-4: the metric of
+ * Section 2, eq. kerr, depends on neither t nor phi), the norm g(u,u) (the constraint
+ * of eq. geo) and Carter's constant Q, are evaluated in FP64 after every step whose
+ * index in the lane's life (its step count over all calls, steps[i]) is a multiple of
+ * monitor_every, and |I - I_0| is folded into a running maximum per invariant.  For
+ * the Hamiltonian formulation E and L_z are read off p_t and p_phi (their drift is
+ * exactly 0) and the norm is g^{mu nu} p_mu p_nu.
+ * monitor: device, 8 * n doubles, component-major (monitor[k * n + i]): rows 0..3 the
+ * reference invariants I_0 = (E, L_z, Q, g(u,u)) of lane i, rows 4..7 the running
+ * maxima of |E - E_0|, |L_z - L_z0|, |Q - Q_0|, |g(u,u) - g_0|.  reset = 1: lanes ACTIVE
+ * on entry take I_0 from their entry state and start from maxima of 0 (rows 0..7
+ * written); reset = 0: rows 0..7 are read and the maxima continue, so that calls of
+ * n_steps / 2 each give bitwise the monitor of one call of n_steps.  Rows of lanes
+ * not ACTIVE on entry are not touched; with n_steps = 0 the call does nothing.
+ * Everything else (precision, formulation, persistent queue, steps_per_chunk, stop
+ * rules, ws) is as in malbec_integrate, and state, status and steps end bitwise as
+ * malbec_integrate leaves them; run->checkpoint_every must be 0 (MALBEC_ENOTSUP).
+ * Errors: MALBEC_EINVAL (also monitor_every < 1, reset not 0/1, monitor NULL with
+ * n > 0), MALBEC_ENOMEM, MALBEC_ENOTSUP, MALBEC_EDEVICE. */
+MALBEC_API int malbec_integrate_monitored(const malbec_run *run, const malbec_batch *b, int64_t n,
+                                          double *state, int32_t *status, int32_t *steps,
+                                          int32_t monitor_every, int32_t reset, double *monitor,
+                                          void *ws, size_t ws_bytes, void *stream);
+
 /* malbec_integrate (FP64, either formulation, one launch) that also records the
  * paper's trajectory output (Section 5: affine parameter tau, coordinate time t and
  * the Cartesian position of Section 2, eq. coord, x = sqrt(r^2 + a^2) sin(theta)

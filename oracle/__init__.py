@@ -83,6 +83,9 @@ def lib():
         "oracle_integrate": (C.c_int, [P(d), vp, i64, P(d), P(i32), P(i32), d, i64, d, d,
                                        C.c_int, C.c_int]),
         "oracle_invariants": (C.c_int, [P(d), vp, i64, P(d), P(d)]),
+        "oracle_invariants_hamiltonian_one": (None, [d, d, P(d), P(d)]),
+        "oracle_integrate_monitored": (C.c_int, [P(d), vp, i64, P(d), P(i32), P(i32), d, i64, d,
+                                                 d, C.c_int, i64, C.c_int, P(d), C.c_int]),
         "oracle_dp45_attempt": (None, [d, d, d, P(d), P(d), P(d)]),
         "oracle_kerr_3p1": (None, [d, d, d, d, P(d)]),
         "oracle_grid_fill_kerr": (None, [d, d, i64, i64, d, d, d, d, P(d)]),
@@ -268,6 +271,36 @@ def integrate(spacetimes, state, h, n_steps, status=None, steps=None, horizon_fa
     lib().oracle_integrate(_dp(Ma), stp, n, _dp(s), _ip(status), _ip(steps), h, n_steps,
                            horizon_factor, r_escape, int(hamiltonian), nthreads)
     return s.reshape(8, n), status, steps
+
+
+def integrate_monitored(spacetimes, state, h, n_steps, every, monitor=None, status=None,
+                        steps=None, horizon_factor=1.01, r_escape=1500.0, hamiltonian=False,
+                        st_of_lane=None, nthreads=0):
+    """Fixed-step RK4 with the invariant monitor every `every` steps of each lane's
+    life (copies).  monitor=None resets (I0 from the entry state, maxima 0); otherwise
+    the given [8, n] monitor continues.  Returns (state, status, steps, monitor)."""
+    state = np.array(state, dtype=np.float64, copy=True)
+    n = state.shape[1]
+    s = np.ascontiguousarray(state.reshape(-1))
+    status = np.zeros(n, np.int32) if status is None else np.array(status, np.int32, copy=True)
+    steps = np.zeros(n, np.int32) if steps is None else np.array(steps, np.int32, copy=True)
+    reset = monitor is None
+    mon = np.full(8 * n, np.nan) if reset else np.array(monitor, np.float64, copy=True).reshape(-1)
+    Ma = _Ma(spacetimes)
+    _keep, stp = _st_ptr(st_of_lane, n)
+    rc = lib().oracle_integrate_monitored(_dp(Ma), stp, n, _dp(s), _ip(status), _ip(steps), h,
+                                          n_steps, horizon_factor, r_escape, int(hamiltonian),
+                                          every, int(reset), _dp(mon), nthreads)
+    if rc:
+        raise ValueError("every must be >= 1")
+    return s.reshape(8, n), status, steps, mon.reshape(8, n)
+
+
+def invariants_hamiltonian_one(M, a, z):
+    z = _f64(z, 8)
+    out = np.zeros(4)
+    lib().oracle_invariants_hamiltonian_one(M, a, _dp(z), _dp(out))
+    return out
 
 
 def dp45_attempt(M, a, h, y):

@@ -471,6 +471,79 @@ int oracle_integrate(const double *Ma, const int32_t *st_of_lane, int64_t n, dou
     return 0;
 }
 
+/* The same four invariants of a canonical state z = (x^mu, p_mu): E = -p_t and
+ * L_z = p_phi directly (the conserved momenta of Sections 3-4), the norm
+ * g^{mu nu} p_mu p_nu with the inverse metric, p_theta as it stands. */
+void oracle_invariants_hamiltonian_one(double M, double a, const double *z, double *out)
+{
+    double gi[4][4];
+    oracle_inverse_metric(M, a, z[1], z[2], &gi[0][0]);
+    const double *p = z + 4;
+    double norm = 0.0;
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) norm += gi[i][j] * p[i] * p[j];
+    double E = -p[0];
+    double Lz = p[3];
+    double s = sin(z[2]), c = cos(z[2]);
+    double mu2 = -norm;
+    double Q = p[2] * p[2] + c * c * (a * a * (mu2 - E * E) + Lz * Lz / (s * s));
+    out[0] = E;
+    out[1] = Lz;
+    out[2] = Q;
+    out[3] = norm;
+}
+
+/* Fixed-step integration with the invariant monitor: after every step whose index
+ * in the lane's life (steps[i] after the step) is a multiple of `every`, the
+ * invariants In of the lane's state update D_k = max(D_k, |In_k - I0_k|).
+ * monitor[8n] (component-major): rows 0..3 I0, rows 4..7 D.  reset != 0: lanes ACTIVE
+ * on entry take I0 from their entry state and D = 0; otherwise both are read.  Lanes
+ * not ACTIVE on entry, and every lane when n_steps = 0, are left untouched. */
+int oracle_integrate_monitored(const double *Ma, const int32_t *st_of_lane, int64_t n,
+                               double *state, int32_t *status, int32_t *steps, double h,
+                               int64_t n_steps, double horizon_factor, double r_escape,
+                               int hamiltonian, int64_t every, int reset, double *monitor,
+                               int nthreads)
+{
+    if (every < 1) return -1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        if (status[i] != ST_ACTIVE || n_steps == 0) continue;
+        int st = st_of_lane ? st_of_lane[i] : 0;
+        double M = Ma[2 * st], a = Ma[2 * st + 1];
+        double y[8], I0[4], D[4], In[4];
+        get_state(state, n, i, y);
+        if (reset) {
+            if (hamiltonian) oracle_invariants_hamiltonian_one(M, a, y, I0);
+            else oracle_invariants_one(M, a, y, I0);
+            for (int k = 0; k < 4; ++k) D[k] = 0.0;
+        } else {
+            for (int k = 0; k < 4; ++k) {
+                I0[k] = monitor[k * n + i];
+                D[k] = monitor[(4 + k) * n + i];
+            }
+        }
+        for (int64_t k = 0; k < n_steps && status[i] == ST_ACTIVE; ++k) {
+            integrate_lane(M, a, h, 1, horizon_factor, r_escape, hamiltonian, y, &status[i]);
+            steps[i] += 1;
+            if (steps[i] % every == 0) {
+                if (hamiltonian) oracle_invariants_hamiltonian_one(M, a, y, In);
+                else oracle_invariants_one(M, a, y, In);
+                for (int c = 0; c < 4; ++c) D[c] = fmax(D[c], fabs(In[c] - I0[c]));
+            }
+        }
+        put_state(state, n, i, y);
+        for (int k = 0; k < 4; ++k) {
+            monitor[k * n + i] = I0[k];
+            monitor[(4 + k) * n + i] = D[k];
+        }
+    }
+    return 0;
+}
+
 /* Invariants of a SoA batch: out[4n] = (E, L_z, Q, g(u,u)) component-major. */
 int oracle_invariants(const double *Ma, const int32_t *st_of_lane, int64_t n, const double *state,
                       double *out)

@@ -113,6 +113,10 @@ EXPORTS = {
     "malbec_integrate": (C.c_int, [C.POINTER(c_run), C.POINTER(c_batch), C.c_int64, C.c_void_p,
                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
                                    C.c_void_p]),
+    "malbec_integrate_monitored": (C.c_int, [C.POINTER(c_run), C.POINTER(c_batch), C.c_int64,
+                                             C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                             C.c_int32, C.c_void_p, C.c_void_p, C.c_size_t,
+                                             C.c_void_p]),
     "malbec_trace_camera": (C.c_int, [C.POINTER(c_camera), C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "malbec_invariants": (C.c_int, [C.POINTER(c_batch), C.c_int64, C.c_void_p, C.c_void_p,
@@ -283,6 +287,42 @@ def integrate(state: torch.Tensor, status: torch.Tensor, steps: torch.Tensor, sp
                                   _ptr(steps, torch.int32, n, "steps"),
                                   _ptr(checkpoints, torch.float64, None, "checkpoints"),
                                   _ptr(ws), ws.numel() if ws is not None else 0, _stream()))
+
+
+def integrate_monitored(state: torch.Tensor, status: torch.Tensor, steps: torch.Tensor, spacetimes,
+                        h: float, n_steps: int, monitor_every: int,
+                        monitor: Optional[torch.Tensor] = None, reset: bool = True,
+                        horizon_factor: float = 1.01, r_escape: float = 1500.0,
+                        precision: str = "f64", fp64_zone_factor: float = 1.2, block: int = 0,
+                        steps_per_chunk: int = 0, st_of_lane: Optional[torch.Tensor] = None,
+                        persistent: bool = False, ws: Optional[torch.Tensor] = None,
+                        formulation: str = "christoffel"):
+    """integrate() with the invariant monitor every monitor_every steps of each lane's
+    life.  monitor [8, n] float64: rows 0..3 the reference (E, L_z, Q, g(u,u)), rows
+    4..7 the running maxima of |I - I_0| (written from the entry state when reset;
+    carried over otherwise).  Returns monitor."""
+    n = state.shape[-1]
+    prec = {"f64": F64, "f32k": F32_KAHAN}[precision]
+    form = {"christoffel": FORM_CHRISTOFFEL, "hamiltonian": FORM_HAMILTONIAN}[formulation]
+    run = c_run(h, n_steps, prec, block, horizon_factor, r_escape, fp64_zone_factor,
+                steps_per_chunk, 0, int(persistent), form)
+    b = _Batch(_spacetimes(spacetimes), st_of_lane, n)
+    if monitor is None:
+        if not reset:
+            raise ValueError("reset=False needs the monitor tensor of the previous call")
+        monitor = torch.full((8, n), float("nan"), dtype=torch.float64, device=state.device)
+    need = workspace_bytes(OP_INTEGRATE, n, int(persistent))
+    if need and ws is None:
+        ws = torch.empty(need, dtype=torch.uint8, device=state.device)
+    _check(lib().malbec_integrate_monitored(C.byref(run), C.byref(b.c), n,
+                                            _ptr(state, torch.float64, 8 * n, "state"),
+                                            _ptr(status, torch.int32, n, "status"),
+                                            _ptr(steps, torch.int32, n, "steps"),
+                                            int(monitor_every), int(bool(reset)),
+                                            _ptr(monitor, torch.float64, 8 * n, "monitor"),
+                                            _ptr(ws), ws.numel() if ws is not None else 0,
+                                            _stream()))
+    return monitor
 
 
 def invariants(state: torch.Tensor, spacetimes, st_of_lane: Optional[torch.Tensor] = None,

@@ -66,6 +66,48 @@ int make_table(const malbec_batch *b, double horizon_factor, double zone_factor,
 
 using namespace malbec;
 
+namespace {
+
+// Argument checks shared by malbec_integrate and malbec_integrate_monitored.
+int check_run(const malbec_run *run, int64_t n, const double *state, const int32_t *status,
+              const int32_t *steps, const double *checkpoints, const void *ws, size_t ws_bytes)
+{
+    if (!run) return fail(MALBEC_EINVAL, "run is NULL");
+    if (n < 0) return fail(MALBEC_EINVAL, "n = %lld < 0", (long long)n);
+    if (n > 0 && (!state || !status || !steps))
+        return fail(MALBEC_EINVAL, "state, status and steps must be non-NULL");
+    if (n > ((int64_t)1 << 40)) return fail(MALBEC_EINVAL, "n too large");
+    if (!(run->h > 0.0) || !isfinite(run->h)) return fail(MALBEC_EINVAL, "h = %g must be > 0", run->h);
+    if (run->n_steps < 0 || run->n_steps > INT32_MAX)
+        return fail(MALBEC_EINVAL, "n_steps = %lld outside [0, 2^31)", (long long)run->n_steps);
+    if (!(run->r_escape > 0.0)) return fail(MALBEC_EINVAL, "r_escape must be > 0");
+    if (run->block < 0 || run->block > 1024 || (run->block % 64) != 0)
+        return fail(MALBEC_EINVAL, "block = %d must be a multiple of 64 in [64, 1024] or 0", run->block);
+    if (run->steps_per_chunk < 0) return fail(MALBEC_EINVAL, "steps_per_chunk < 0");
+    if (run->checkpoint_every < 0) return fail(MALBEC_EINVAL, "checkpoint_every < 0");
+    if (run->checkpoint_every > 0 && !checkpoints)
+        return fail(MALBEC_EINVAL, "checkpoint_every > 0 needs a checkpoints buffer");
+    if (run->persistent != 0 && run->persistent != 1) return fail(MALBEC_EINVAL, "persistent must be 0 or 1");
+    if (run->persistent && run->checkpoint_every > 0)
+        return fail(MALBEC_ENOTSUP, "checkpoints need persistent = 0");
+    if (run->formulation != MALBEC_FORM_CHRISTOFFEL && run->formulation != MALBEC_FORM_HAMILTONIAN)
+        return fail(MALBEC_EINVAL, "unknown formulation %d", run->formulation);
+    if (run->formulation == MALBEC_FORM_HAMILTONIAN) {
+        if (run->checkpoint_every > 0)
+            return fail(MALBEC_ENOTSUP, "checkpoints need the Christoffel formulation");
+    }
+    size_t need = malbec_workspace_bytes(MALBEC_OP_INTEGRATE, n, run->persistent);
+    if (ws_bytes < need || (need > 0 && !ws))
+        return fail(MALBEC_ENOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, need);
+    if (run->precision == MALBEC_F32_KAHAN && !(run->fp64_zone_factor >= 1.0))
+        return fail(MALBEC_EINVAL, "fp64_zone_factor = %g must be >= 1", run->fp64_zone_factor);
+    if (run->precision != MALBEC_F64 && run->precision != MALBEC_F32_KAHAN)
+        return fail(MALBEC_EINVAL, "unknown precision %d", run->precision);
+    return MALBEC_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *malbec_last_error(void) { return g_err; }
@@ -125,42 +167,20 @@ int malbec_init_particles(const malbec_ic_spec *spec, const malbec_batch *b, int
     return launch_init(*spec, T, b->st_of_lane, n, state, consts, attempts, (hipStream_t)stream);
 }
 
+
 int malbec_integrate(const malbec_run *run, const malbec_batch *b, int64_t n, double *state,
                      int32_t *status, int32_t *steps, double *checkpoints, void *ws,
                      size_t ws_bytes, void *stream)
 {
     clear_error();
-    if (!run) return fail(MALBEC_EINVAL, "run is NULL");
-    if (n < 0) return fail(MALBEC_EINVAL, "n = %lld < 0", (long long)n);
-    if (n > 0 && (!state || !status || !steps))
-        return fail(MALBEC_EINVAL, "state, status and steps must be non-NULL");
-    if (n > ((int64_t)1 << 40)) return fail(MALBEC_EINVAL, "n too large");
-    if (!(run->h > 0.0) || !isfinite(run->h)) return fail(MALBEC_EINVAL, "h = %g must be > 0", run->h);
-    if (run->n_steps < 0 || run->n_steps > INT32_MAX)
-        return fail(MALBEC_EINVAL, "n_steps = %lld outside [0, 2^31)", (long long)run->n_steps);
-    if (!(run->r_escape > 0.0)) return fail(MALBEC_EINVAL, "r_escape must be > 0");
-    if (run->block < 0 || run->block > 1024 || (run->block % 64) != 0)
-        return fail(MALBEC_EINVAL, "block = %d must be a multiple of 64 in [64, 1024] or 0", run->block);
-    if (run->steps_per_chunk < 0) return fail(MALBEC_EINVAL, "steps_per_chunk < 0");
-    if (run->checkpoint_every < 0) return fail(MALBEC_EINVAL, "checkpoint_every < 0");
-    if (run->checkpoint_every > 0 && !checkpoints)
-        return fail(MALBEC_EINVAL, "checkpoint_every > 0 needs a checkpoints buffer");
-    if (run->persistent != 0 && run->persistent != 1) return fail(MALBEC_EINVAL, "persistent must be 0 or 1");
-    if (run->persistent && run->checkpoint_every > 0)
-        return fail(MALBEC_ENOTSUP, "checkpoints need persistent = 0");
-    if (run->formulation != MALBEC_FORM_CHRISTOFFEL && run->formulation != MALBEC_FORM_HAMILTONIAN)
-        return fail(MALBEC_EINVAL, "unknown formulation %d", run->formulation);
-    if (run->formulation == MALBEC_FORM_HAMILTONIAN) {
-        if (run->checkpoint_every > 0)
-            return fail(MALBEC_ENOTSUP, "checkpoints need the Christoffel formulation");
-    }
-    size_t need = malbec_workspace_bytes(MALBEC_OP_INTEGRATE, n, run->persistent);
-    if (ws_bytes < need || (need > 0 && !ws))
-        return fail(MALBEC_ENOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, need);
+    int rc = check_run(run, n, state, status, steps, checkpoints, ws, ws_bytes);
+    if (rc) return rc;
     double zone = run->precision == MALBEC_F32_KAHAN ? run->fp64_zone_factor : 1.0;
     StTable T;
-    int rc = make_table(b, run->horizon_factor, zone, T);
+    rc = make_table(b, run->horizon_factor, zone, T);
     if (rc) return rc;
+    if (run->precision == MALBEC_F32_KAHAN && run->checkpoint_every > 0)
+        return fail(MALBEC_ENOTSUP, "checkpoints are FP64 only");
     if (n == 0 || run->n_steps == 0) {
         if (run->checkpoint_every > 0 && n > 0)
             return fail(MALBEC_ENOTSUP, "checkpoints with n_steps = 0");
@@ -169,15 +189,33 @@ int malbec_integrate(const malbec_run *run, const malbec_batch *b, int64_t n, do
     if (run->precision == MALBEC_F64)
         return launch_integrate_f64(*run, T, b->st_of_lane, n, state, status, steps, checkpoints,
                                     ws, (hipStream_t)stream);
-    if (run->precision == MALBEC_F32_KAHAN) {
-        if (run->checkpoint_every > 0)
-            return fail(MALBEC_ENOTSUP, "checkpoints are FP64 only");
-        if (!(run->fp64_zone_factor >= 1.0))
-            return fail(MALBEC_EINVAL, "fp64_zone_factor = %g must be >= 1", run->fp64_zone_factor);
-        return launch_integrate_f32k(*run, T, b->st_of_lane, n, state, status, steps, ws,
-                                     (hipStream_t)stream);
-    }
-    return fail(MALBEC_EINVAL, "unknown precision %d", run->precision);
+    return launch_integrate_f32k(*run, T, b->st_of_lane, n, state, status, steps, ws,
+                                 (hipStream_t)stream);
+}
+
+int malbec_integrate_monitored(const malbec_run *run, const malbec_batch *b, int64_t n,
+                               double *state, int32_t *status, int32_t *steps,
+                               int32_t monitor_every, int32_t reset, double *monitor, void *ws,
+                               size_t ws_bytes, void *stream)
+{
+    clear_error();
+    if (run && run->checkpoint_every != 0)
+        return fail(MALBEC_ENOTSUP, "the monitored integration writes no checkpoints");
+    int rc = check_run(run, n, state, status, steps, nullptr, ws, ws_bytes);
+    if (rc) return rc;
+    if (monitor_every < 1) return fail(MALBEC_EINVAL, "monitor_every = %d must be >= 1", monitor_every);
+    if (reset != 0 && reset != 1) return fail(MALBEC_EINVAL, "reset must be 0 or 1");
+    if (n > 0 && !monitor) return fail(MALBEC_EINVAL, "monitor must be non-NULL");
+    double zone = run->precision == MALBEC_F32_KAHAN ? run->fp64_zone_factor : 1.0;
+    StTable T;
+    rc = make_table(b, run->horizon_factor, zone, T);
+    if (rc) return rc;
+    if (n == 0 || run->n_steps == 0) return MALBEC_OK;
+    if (run->precision == MALBEC_F64)
+        return launch_monitor_f64(*run, T, b->st_of_lane, n, state, status, steps, monitor_every,
+                                  reset, monitor, ws, (hipStream_t)stream);
+    return launch_monitor_f32k(*run, T, b->st_of_lane, n, state, status, steps, monitor_every,
+                               reset, monitor, ws, (hipStream_t)stream);
 }
 
 int malbec_trace_camera(const malbec_camera *cam, int32_t *status, int32_t *steps, double *hit,

@@ -6,6 +6,7 @@
 // launch; the work is FP64 VALU arithmetic.  Spacetime constants come from the
 // kernel arguments (uniform batch) or from an LDS copy of the table (mixed batch).
 #include "internal.hpp"
+#include "monitor.hpp"
 #include "persistent.hpp"
 
 namespace malbec {
@@ -188,6 +189,7 @@ struct F64Prog {
         A.status[i] = L.st;
         A.steps[i] += L.taken;
     }
+    __device__ static __forceinline__ void state64(const Lane &L, double y[8]) { copy8(y, L.y); }
 };
 
 template <bool MULTI, bool HAM>
@@ -200,6 +202,59 @@ __global__ void __launch_bounds__(256) rk4_f64_persistent_kernel(IntArgs A, StTa
     __syncthreads();
     F64Prog<HAM> P{A, lds_st, MULTI, T.n_st};
     persistent_loop(P, A.n, counter, chunk);
+}
+
+// The FP64 step with the invariant monitor folded in every K steps: one thread per
+// lane, or the persistent work queue.
+template <bool HAM>
+__global__ void __launch_bounds__(256) rk4_f64_monitor_kernel(IntArgs A, StTable T, MonArgs MA,
+                                                              int32_t multi)
+{
+    __shared__ Spacetime lds_st[kMaxSt];
+    for (int k = threadIdx.x; k < T.n_st; k += blockDim.x) lds_st[k] = T.st[k];
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    MonProg<F64Prog<HAM>, HAM> P{F64Prog<HAM>{A, lds_st, multi != 0, T.n_st}, MA};
+    typename MonProg<F64Prog<HAM>, HAM>::Lane L;
+    if (!P.load(i, L)) return;
+    while (!P.step(L)) {
+    }
+    P.store(i, L);
+}
+
+template <bool HAM>
+__global__ void __launch_bounds__(256) rk4_f64_monitor_persistent_kernel(IntArgs A, StTable T,
+                                                                         MonArgs MA, int32_t multi,
+                                                                         unsigned long long *counter,
+                                                                         int32_t chunk)
+{
+    __shared__ Spacetime lds_st[kMaxSt];
+    for (int k = threadIdx.x; k < T.n_st; k += blockDim.x) lds_st[k] = T.st[k];
+    __syncthreads();
+    MonProg<F64Prog<HAM>, HAM> P{F64Prog<HAM>{A, lds_st, multi != 0, T.n_st}, MA};
+    persistent_loop(P, A.n, counter, chunk);
+}
+
+template <bool HAM>
+int launch_monitor(const IntArgs &A, const StTable &T, const MonArgs &MA, bool multi, int block,
+                   bool persistent, int32_t sub, unsigned long long *counter, hipStream_t s)
+{
+    if (persistent) {
+        int grid = 0;
+        int rc = persistent_grid((const void *)rk4_f64_monitor_persistent_kernel<HAM>, block, A.n, grid);
+        if (rc) return rc;
+        hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(1), 0, s, counter);
+        MALBEC_LAUNCH_CHECK("zero_u64_kernel");
+        hipLaunchKernelGGL((rk4_f64_monitor_persistent_kernel<HAM>), dim3(grid), dim3(block), 0, s,
+                           A, T, MA, (int32_t)multi, counter, sub);
+        MALBEC_LAUNCH_CHECK("rk4_f64_monitor_persistent_kernel");
+        return MALBEC_OK;
+    }
+    hipLaunchKernelGGL((rk4_f64_monitor_kernel<HAM>), dim3(grid_for(A.n, block)), dim3(block), 0, s,
+                       A, T, MA, (int32_t)multi);
+    MALBEC_LAUNCH_CHECK("rk4_f64_monitor_kernel");
+    return MALBEC_OK;
 }
 
 template <bool MULTI, bool CKPT, bool HAM>
@@ -277,6 +332,47 @@ int launch_integrate_f64(const malbec_run &run, const StTable &T, const int32_t 
         else
             rc = multi ? launch_kernel<true, false, false>(A, T, block, s)
                        : launch_kernel<false, false, false>(A, T, block, s);
+        if (rc) return rc;
+    }
+    return MALBEC_OK;
+}
+
+int launch_monitor_f64(const malbec_run &run, const StTable &T, const int32_t *st_of_lane,
+                       int64_t n, double *state, int32_t *status, int32_t *steps, int32_t every,
+                       int32_t reset, double *mon, void *ws, hipStream_t s)
+{
+    const int block = run.block > 0 ? run.block : 256;
+    if (block > 256) return fail(MALBEC_EINVAL, "block %d exceeds the kernel's launch bound 256", block);
+    const bool multi = st_of_lane != nullptr && T.n_st > 1;
+    const bool ham = run.formulation == MALBEC_FORM_HAMILTONIAN;
+    const int64_t total = run.n_steps;
+    IntArgs A;
+    A.n = n;
+    A.state = state;
+    A.status = status;
+    A.steps = steps;
+    A.st_of_lane = multi ? st_of_lane : nullptr;
+    A.ckpt = nullptr;
+    A.h = run.h;
+    A.r_escape = run.r_escape;
+    A.ck_every = 0;
+    A.ck_last = 0;
+    A.k0 = 0;
+    MonArgs MA{mon, steps, n, every, reset};
+    unsigned long long *counter = (unsigned long long *)ws;
+    if (run.persistent) {
+        A.n_steps = (int32_t)total;
+        const int32_t sub = run.steps_per_chunk > 0 ? run.steps_per_chunk : 64;
+        return ham ? launch_monitor<true>(A, T, MA, multi, block, true, sub, counter, s)
+                   : launch_monitor<false>(A, T, MA, multi, block, true, sub, counter, s);
+    }
+    const int64_t chunk = run.steps_per_chunk > 0 ? run.steps_per_chunk : total;
+    for (int64_t k0 = 0; k0 < total; k0 += chunk) {
+        A.k0 = (int32_t)k0;
+        A.n_steps = (int32_t)((total - k0) < chunk ? (total - k0) : chunk);
+        MA.reset = (k0 == 0) ? reset : 0;
+        int rc = ham ? launch_monitor<true>(A, T, MA, multi, block, false, 0, counter, s)
+                     : launch_monitor<false>(A, T, MA, multi, block, false, 0, counter, s);
         if (rc) return rc;
     }
     return MALBEC_OK;

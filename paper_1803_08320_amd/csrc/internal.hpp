@@ -50,6 +50,13 @@ int launch_integrate_f64(const malbec_run &run, const StTable &T, const int32_t 
 int launch_integrate_f32k(const malbec_run &run, const StTable &T, const int32_t *st_of_lane,
                           int64_t n, double *state, int32_t *status, int32_t *steps, void *ws,
                           hipStream_t s);
+// The same integrators with the invariant monitor every `every` steps (mon: 8n).
+int launch_monitor_f64(const malbec_run &run, const StTable &T, const int32_t *st_of_lane,
+                       int64_t n, double *state, int32_t *status, int32_t *steps, int32_t every,
+                       int32_t reset, double *mon, void *ws, hipStream_t s);
+int launch_monitor_f32k(const malbec_run &run, const StTable &T, const int32_t *st_of_lane,
+                        int64_t n, double *state, int32_t *status, int32_t *steps, int32_t every,
+                        int32_t reset, double *mon, void *ws, hipStream_t s);
 // Grid of a persistent kernel: resident blocks per CU x CUs, capped by the blocks the
 // work needs.
 int persistent_grid(const void *kernel, int block, int64_t n_items, int &grid);

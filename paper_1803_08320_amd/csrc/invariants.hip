@@ -1,4 +1,5 @@
-// Invariant monitor: (E, L_z, Carter Q, g(u,u)) of each lane in FP64.
+// Invariants (E, L_z, Carter Q, g(u,u)) of each lane in FP64, from lane_invariants of
+// monitor.hpp:
 //   E   = -(g_tt u^t + g_tphi u^phi)            (conserved: dp_t/dtau = 0, Sections 3-4)
 //   L_z = g_tphi u^t + g_phiphi u^phi           (conserved: dp_phi/dtau = 0)
 //   Q   = (rho^2 u^theta)^2 + cos^2 [a^2 (mu^2 - E^2) + L_z^2 / sin^2],  mu^2 = -g(u,u)
@@ -8,6 +9,7 @@
 // u^mu = g^{mu nu} p_nu (raise), Section 2, eq. kerr.
 #include "ic_device.hpp"
 #include "internal.hpp"
+#include "monitor.hpp"
 
 namespace malbec {
 
@@ -26,30 +28,12 @@ __global__ void __launch_bounds__(256) invariants_kernel(const double *__restric
         return;
     }
     const Spacetime S = T.st[sid];
-    const double M = S.M, a = S.a;
-    const double r = state[1 * n + i], th = state[2 * n + i];
-    const double ut = state[4 * n + i], ur = state[5 * n + i];
-    const double uth = state[6 * n + i], uph = state[7 * n + i];
-    double s, c;
-    sincos(th, &s, &c);
-    const double a2 = a * a, s2 = s * s, r2 = r * r;
-    const double rho2 = r2 + a2 * c * c;
-    const double Delta = r2 - 2.0 * M * r + a2;
-    const double q = 2.0 * M * r / rho2;
-    const double gtt = q - 1.0;
-    const double gtp = -a * q * s2;
-    const double gpp = (r2 + a2 + a2 * q * s2) * s2;
-    const double grr = rho2 / Delta;
-    const double norm = gtt * ut * ut + 2.0 * gtp * ut * uph + gpp * uph * uph + grr * ur * ur +
-                        rho2 * uth * uth;
-    const double E = -(gtt * ut + gtp * uph);
-    const double Lz = gtp * ut + gpp * uph;
-    const double pth = rho2 * uth;
-    const double Q = pth * pth + c * c * (a2 * (-norm - E * E) + Lz * Lz / s2);
-    out[0 * n + i] = E;
-    out[1 * n + i] = Lz;
-    out[2 * n + i] = Q;
-    out[3 * n + i] = norm;
+    double y[8], v[4];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) y[k] = state[k * n + i];
+    lane_invariants<false>(S.M, S.a, y, v);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) out[k * n + i] = v[k];
 }
 
 __global__ void __launch_bounds__(256) convert_kernel(double *__restrict__ state,

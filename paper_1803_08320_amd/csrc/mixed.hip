@@ -9,6 +9,7 @@
 // that starts inside r_zone runs entirely in FP64 on hi + lo and splits the result
 // back.  The double state in HBM is hi + lo at load (split) and at store (sum).
 #include "internal.hpp"
+#include "monitor.hpp"
 #include "persistent.hpp"
 
 namespace malbec {
@@ -190,6 +191,11 @@ struct MixProg {
         A.status[i] = L.st;
         A.steps[i] += L.taken;
     }
+    __device__ static __forceinline__ void state64(const Lane &L, double y[8])
+    {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) y[k] = (double)L.hi[k] + (double)L.lo[k];
+    }
 };
 
 template <bool MULTI, bool HAM>
@@ -218,6 +224,58 @@ __global__ void __launch_bounds__(256) rk4_f32k_persistent_kernel(MixArgs A, StT
     __syncthreads();
     MixProg<HAM> P{A, lds_st, MULTI, T.n_st};
     persistent_loop(P, A.n, counter, chunk);
+}
+
+// The compensated step with the invariant monitor (FP64, on hi + lo) every K steps.
+template <bool HAM>
+__global__ void __launch_bounds__(256) rk4_f32k_monitor_kernel(MixArgs A, StTable T, MonArgs MA,
+                                                               int32_t multi)
+{
+    __shared__ Spacetime lds_st[kMaxSt];
+    for (int k = threadIdx.x; k < T.n_st; k += blockDim.x) lds_st[k] = T.st[k];
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    MonProg<MixProg<HAM>, HAM> P{MixProg<HAM>{A, lds_st, multi != 0, T.n_st}, MA};
+    typename MonProg<MixProg<HAM>, HAM>::Lane L;
+    if (!P.load(i, L)) return;
+    while (!P.step(L)) {
+    }
+    P.store(i, L);
+}
+
+template <bool HAM>
+__global__ void __launch_bounds__(256) rk4_f32k_monitor_persistent_kernel(MixArgs A, StTable T,
+                                                                          MonArgs MA, int32_t multi,
+                                                                          unsigned long long *counter,
+                                                                          int32_t chunk)
+{
+    __shared__ Spacetime lds_st[kMaxSt];
+    for (int k = threadIdx.x; k < T.n_st; k += blockDim.x) lds_st[k] = T.st[k];
+    __syncthreads();
+    MonProg<MixProg<HAM>, HAM> P{MixProg<HAM>{A, lds_st, multi != 0, T.n_st}, MA};
+    persistent_loop(P, A.n, counter, chunk);
+}
+
+template <bool HAM>
+int launch_monitor(const MixArgs &A, const StTable &T, const MonArgs &MA, bool multi, int block,
+                   bool persistent, int32_t sub, unsigned long long *counter, hipStream_t s)
+{
+    if (persistent) {
+        int grid = 0;
+        int rc = persistent_grid((const void *)rk4_f32k_monitor_persistent_kernel<HAM>, block, A.n, grid);
+        if (rc) return rc;
+        hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(1), 0, s, counter);
+        MALBEC_LAUNCH_CHECK("zero_u64_kernel");
+        hipLaunchKernelGGL((rk4_f32k_monitor_persistent_kernel<HAM>), dim3(grid), dim3(block), 0, s,
+                           A, T, MA, (int32_t)multi, counter, sub);
+        MALBEC_LAUNCH_CHECK("rk4_f32k_monitor_persistent_kernel");
+        return MALBEC_OK;
+    }
+    hipLaunchKernelGGL((rk4_f32k_monitor_kernel<HAM>), dim3(grid_for(A.n, block)), dim3(block), 0, s,
+                       A, T, MA, (int32_t)multi);
+    MALBEC_LAUNCH_CHECK("rk4_f32k_monitor_kernel");
+    return MALBEC_OK;
 }
 
 }  // namespace
@@ -276,6 +334,42 @@ int launch_integrate_f32k(const malbec_run &run, const StTable &T, const int32_t
     for (int64_t k0 = 0; k0 < total; k0 += chunk) {
         A.n_steps = (int32_t)((total - k0) < chunk ? (total - k0) : chunk);
         int rc = go(false, 0);
+        if (rc) return rc;
+    }
+    return MALBEC_OK;
+}
+
+int launch_monitor_f32k(const malbec_run &run, const StTable &T, const int32_t *st_of_lane,
+                        int64_t n, double *state, int32_t *status, int32_t *steps, int32_t every,
+                        int32_t reset, double *mon, void *ws, hipStream_t s)
+{
+    const int block = run.block > 0 ? run.block : 256;
+    if (block > 256) return fail(MALBEC_EINVAL, "block %d exceeds the kernel's launch bound 256", block);
+    const bool multi = st_of_lane != nullptr && T.n_st > 1;
+    const bool ham = run.formulation == MALBEC_FORM_HAMILTONIAN;
+    const int64_t total = run.n_steps;
+    MixArgs A;
+    A.n = n;
+    A.state = state;
+    A.status = status;
+    A.steps = steps;
+    A.st_of_lane = multi ? st_of_lane : nullptr;
+    A.h = run.h;
+    A.r_escape = run.r_escape;
+    MonArgs MA{mon, steps, n, every, reset};
+    unsigned long long *counter = (unsigned long long *)ws;
+    if (run.persistent) {
+        A.n_steps = (int32_t)total;
+        const int32_t sub = run.steps_per_chunk > 0 ? run.steps_per_chunk : 64;
+        return ham ? launch_monitor<true>(A, T, MA, multi, block, true, sub, counter, s)
+                   : launch_monitor<false>(A, T, MA, multi, block, true, sub, counter, s);
+    }
+    const int64_t chunk = run.steps_per_chunk > 0 ? run.steps_per_chunk : total;
+    for (int64_t k0 = 0; k0 < total; k0 += chunk) {
+        A.n_steps = (int32_t)((total - k0) < chunk ? (total - k0) : chunk);
+        MA.reset = (k0 == 0) ? reset : 0;
+        int rc = ham ? launch_monitor<true>(A, T, MA, multi, block, false, 0, counter, s)
+                     : launch_monitor<false>(A, T, MA, multi, block, false, 0, counter, s);
         if (rc) return rc;
     }
     return MALBEC_OK;

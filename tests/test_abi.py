@@ -119,6 +119,24 @@ def test_integrate_argument_errors(m, kw, sts, n, expect):
     assert m.last_error() != ""
 
 
+@pytest.mark.parametrize("kw,every,reset,mon,expect", [
+    (dict(), 0, 1, FAKE, -1),                       # monitor_every < 1
+    (dict(), 10, 2, FAKE, -1),                      # reset not 0 / 1
+    (dict(), 10, 1, None, -1),                      # no monitor buffer
+    (dict(h=-1.0), 10, 1, FAKE, -1),                # the run's own checks apply
+    (dict(precision=1, fp64_zone_factor=0.5), 10, 1, FAKE, -1),
+    (dict(checkpoint_every=4), 10, 1, FAKE, -4),    # no checkpoints here
+    (dict(persistent=1), 10, 1, FAKE, -2),          # persistent needs a workspace
+])
+def test_monitored_argument_errors(m, kw, every, reset, mon, expect):
+    run = _run(m, **kw)
+    arr, b = _batch(m)
+    rc = m.lib().malbec_integrate_monitored(C.byref(run), C.byref(b), 4, FAKE, FAKE, FAKE, every,
+                                            reset, mon, None, 0, None)
+    assert rc == expect
+    assert m.last_error() != ""
+
+
 def test_hamiltonian_with_checkpoints_is_unsupported(m):
     run = _run(m, formulation=1, checkpoint_every=4)
     arr, b = _batch(m)

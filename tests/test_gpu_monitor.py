@@ -1,0 +1,178 @@
+"""GPU parity of the in-loop invariant monitor (malbec_integrate_monitored) against the
+oracle's, and against the unmonitored integrator and the invariant kernel."""
+import math
+
+import numpy as np
+import pytest
+
+from parity import TOL_F64, compare, mixed_rel
+
+pytestmark = pytest.mark.gpu
+
+KERR_RANGES = ((5.0, 50.0), (math.pi / 4, 3 * math.pi / 4), (0.92, 0.98), (2.5, 4.5), (0.0, 12.0))
+
+
+@pytest.fixture(scope="module")
+def m():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1803_08320_amd as m
+    m.lib()
+    return m
+
+
+def to_dev(x, dtype=None):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype).cuda()
+
+
+def lower(orc, sts, s, sol=None):
+    z = s.copy()
+    for i in range(s.shape[1]):
+        M, a = sts[0 if sol is None else sol[i]]
+        z[4:, i] = orc.metric(M, a, s[1, i], s[2, i]) @ s[4:, i]
+    return z
+
+
+def run_mon(m, sts, s0, h, n_steps, every, sol=None, monitor=None, reset=True, status=None,
+            steps=None, **kw):
+    import torch
+    n = s0.shape[1]
+    state = to_dev(s0, torch.float64)
+    stt = to_dev(np.zeros(n, np.int32) if status is None else status, torch.int32)
+    spp = to_dev(np.zeros(n, np.int32) if steps is None else steps, torch.int32)
+    mon = None if monitor is None else to_dev(monitor, torch.float64)
+    mon = m.integrate_monitored(state, stt, spp, sts, h, n_steps, every, monitor=mon, reset=reset,
+                                st_of_lane=None if sol is None else to_dev(sol, torch.int32), **kw)
+    torch.cuda.synchronize()
+    return state.cpu().numpy(), stt.cpu().numpy(), spp.cpu().numpy(), mon.cpu().numpy()
+
+
+def run_plain(m, sts, s0, h, n_steps, sol=None, **kw):
+    import torch
+    n = s0.shape[1]
+    state = to_dev(s0, torch.float64)
+    status, steps = m.new_lane_arrays(n)
+    m.integrate(state, status, steps, sts, h=h, n_steps=n_steps,
+                st_of_lane=None if sol is None else to_dev(sol, torch.int32), **kw)
+    torch.cuda.synchronize()
+    return state.cpu().numpy(), status.cpu().numpy(), steps.cpu().numpy()
+
+
+SPINS = [(1.0, 0.0), (1.0, 0.5), (1.0, 0.9)]
+
+
+@pytest.mark.parametrize("formulation", ["christoffel", "hamiltonian"])
+@pytest.mark.parametrize("persistent", [False, True])
+def test_monitor_matches_oracle(m, orc, formulation, persistent):
+    """Three spins in one launch, 700 lanes (several blocks and a ragged tail), h = 0.1
+    (the paper's benchmark step), 2,000 steps monitored every 40: states as in every
+    parity test; reference invariants to rounding; the drift maxima (from the rounding
+    level up to ~1e-8 at this h) to 1e-3 of themselves or 1e-12 absolute."""
+    ham = formulation == "hamiltonian"
+    n = 700
+    sol = (np.arange(n) % 3).astype(np.int32)
+    rc, s0, _, _ = orc.ic_constants(81, SPINS, n, KERR_RANGES, st_of_lane=sol)
+    y0 = lower(orc, SPINS, s0, sol) if ham else s0
+    got = run_mon(m, SPINS, y0, 0.1, 2000, 40, sol=sol, persistent=persistent,
+                  formulation=formulation)
+    ref = orc.integrate_monitored(SPINS, y0, 0.1, 2000, 40, hamiltonian=ham, st_of_lane=sol)
+    for k in range(3):
+        sel = sol == k
+        compare(orc, [SPINS[k]], y0[:, sel], got[0][:, sel], got[1][sel], got[2][sel],
+                ref[0][:, sel], ref[1][sel], ref[2][sel],
+                lambda p0, k=k: orc.integrate([SPINS[k]], p0, 0.1, 2000, hamiltonian=ham))
+    I0g, I0r = got[3][:4], ref[3][:4]
+    assert np.all(np.abs(I0g - I0r) <= 1e-12 * (np.abs(I0r) + 1.0))
+    # drift maxima on the lanes whose trajectories agree to the parity tolerance
+    good = (mixed_rel(got[0], ref[0]) <= TOL_F64) & (got[1] == ref[1]) & (got[2] == ref[2])
+    assert good.mean() > 0.98
+    Dg, Dr = got[3][4:][:, good], ref[3][4:][:, good]
+    assert np.all(np.abs(Dg - Dr) <= 1e-3 * Dr + 1e-12 * (np.abs(I0r[:, good]) + 1.0))
+    if ham:
+        assert np.all(Dg[0] == 0.0) and np.all(Dg[1] == 0.0)
+    assert (ref[1] == 1).sum() > 10  # Schwarzschild draws plunge
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32k"])
+@pytest.mark.parametrize("formulation", ["christoffel", "hamiltonian"])
+@pytest.mark.parametrize("persistent", [False, True])
+def test_monitored_state_is_the_integrators(m, orc, precision, formulation, persistent):
+    """The monitor only reads: state, status and steps are bitwise those of
+    malbec_integrate with the same controls."""
+    st = [(1.0, 0.7)]
+    rc, s0, _, _ = orc.ic_constants(82, st, 777, KERR_RANGES)
+    y0 = lower(orc, st, s0) if formulation == "hamiltonian" else s0
+    kw = dict(precision=precision, formulation=formulation, persistent=persistent)
+    a = run_mon(m, st, y0, 0.05, 1500, 7, **kw)
+    b = run_plain(m, st, y0, 0.05, 1500, **kw)
+    for x, y in zip(a[:3], b):
+        assert np.array_equal(x, y)
+    if formulation == "hamiltonian":
+        act = a[1] == 0
+        assert np.all(a[3][4][act] == 0.0) and np.all(a[3][5][act] == 0.0)
+
+
+def test_monitor_is_the_invariant_kernel_every_K_steps(m, orc):
+    """Running maximum over chunked calls of K steps with malbec_invariants in between
+    equals the in-loop monitor; chunked and resumed monitored calls equal one call."""
+    import torch
+    st = [(1.0, 0.9)]
+    n, K, chunks = 500, 50, 30
+    rc, s0, _, _ = orc.ic_constants(83, st, n, KERR_RANGES)
+    one = run_mon(m, st, s0, 0.05, K * chunks, K)
+    state = to_dev(s0, torch.float64)
+    status, steps = m.new_lane_arrays(n)
+    I0 = m.invariants(state, st).cpu().numpy()
+    D = np.zeros((4, n))
+    for _ in range(chunks):
+        m.integrate(state, status, steps, st, h=0.05, n_steps=K)
+        I = m.invariants(state, st).cpu().numpy()
+        D = np.fmax(D, np.abs(I - I0))
+    torch.cuda.synchronize()
+    # a lane that stops mid-chunk is monitored at its next multiple of K only if it was
+    # still stepping then; compare the lanes that stay active throughout
+    act = one[1] == 0
+    assert act.mean() > 0.95
+    assert np.array_equal(one[3][:4], I0)
+    assert np.array_equal(one[3][4:][:, act], D[:, act])
+    # resumed (reset = 0) and launch-chunked calls give the same bits
+    half = run_mon(m, st, s0, 0.05, K * chunks // 2, K)
+    two = run_mon(m, st, half[0], 0.05, K * chunks // 2, K, monitor=half[3], reset=False,
+                  status=half[1], steps=half[2])
+    split = run_mon(m, st, s0, 0.05, K * chunks, K, steps_per_chunk=333)
+    for x, y, z in zip(one, two, split):
+        assert np.array_equal(x, y) and np.array_equal(x, z)
+
+
+def test_f32k_monitor_bounds(m, orc):
+    """FP32-compensated state, FP64 monitor: the drift maxima stay within the stated
+    accuracy of that path and include the end state's drift."""
+    st = [(1.0, 0.9)]
+    rc, s0, c0, _ = orc.ic_constants(84, st, 1000, KERR_RANGES)
+    import torch
+    got = run_mon(m, st, s0, 0.02, 20000, 500, precision="f32k")
+    act = got[1] == 0
+    I1 = m.invariants(to_dev(got[0], torch.float64), st).cpu().numpy()
+    D = got[3][4:]
+    assert np.all(D[:, act] >= np.abs(I1 - got[3][:4])[:, act])
+    assert np.quantile(D[0][act] / np.abs(got[3][0][act]), 0.99) < 1e-5
+    q = act & (c0[2] >= 0.1)
+    assert np.quantile(D[2][q] / np.abs(got[3][2][q]), 0.99) < 1e-4
+
+
+def test_inactive_lanes_and_empty_calls(m, orc):
+    import torch
+    st = [(1.0, 0.7)]
+    rc, s0, _, _ = orc.ic_constants(85, st, 6, KERR_RANGES)
+    status = np.array([0, 2, 0, 1, 0, 0], np.int32)
+    got = run_mon(m, st, s0, 0.1, 10, 5, status=status)
+    ref = orc.integrate_monitored(st, s0, 0.1, 10, 5, status=status)
+    for i in (1, 3):
+        assert np.all(np.isnan(got[3][:, i])) and np.array_equal(got[0][:, i], s0[:, i])
+    assert np.array_equal(got[1], ref[1]) and np.array_equal(got[2], ref[2])
+    state = to_dev(s0, torch.float64)
+    stt, spp = m.new_lane_arrays(6)
+    mon = m.integrate_monitored(state, stt, spp, st, 0.1, 0, 5)
+    assert torch.isnan(mon).all() and torch.equal(state.cpu(), torch.as_tensor(s0))
