@@ -37,8 +37,8 @@ PEAK_FP64_VECTOR_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 128 FP64 flop/clk/CU
 # taken again.
 KERNEL_SOURCES = ("integrate.hip", "kerr_device.hpp", "kerr_accel.hpp", "ham_accel.hpp",
                   "persistent.hpp")
-TRAFFIC = {"sources_sha256": "c2c1af2eede84a5e440a567a814f6f3727a0f51d8e1f7009b5c3dc9aa0741a1b",
-           "fetch_kib": 36949.5, "fetch_scale": 1048576 / 524308.1875,
+TRAFFIC = {"sources_sha256": "85ac975dc28eadd49fe721ec0d3c4ac7834897bc6c8f8ae69d85a77086b88ce8",
+           "fetch_kib": 36951.625, "fetch_scale": 1048576 / 524307.3125,
            "write_kib": 73728.0, "write_scale": 1048576 / 1048576.0}
 
 

@@ -74,6 +74,8 @@ __global__ void __launch_bounds__(256) rk4_f64_kernel(IntArgs A, StTable T)
         }
     }
     const Spacetime S = MULTI ? lds_st[sid] : T.st[0];
+    // first thread of this wavefront (wave-uniform, held in a scalar register)
+    const int32_t wave0 = __builtin_amdgcn_readfirstlane((int32_t)threadIdx.x) & ~63;
 
     double y[8];
 #pragma unroll
@@ -105,10 +107,14 @@ __global__ void __launch_bounds__(256) rk4_f64_kernel(IntArgs A, StTable T)
                 break;
             }
         }
+        // the lane's index rebuilt from wave-uniform values and its position in the
+        // wavefront: no per-lane address stays live across the loop
+        const int64_t ie = (int64_t)blockIdx.x * blockDim.x + wave0 +
+                           (int32_t)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
 #pragma unroll
-        for (int k = 0; k < 8; ++k) A.state[k * A.n + i] = y[k];
-        A.status[i] = st;
-        A.steps[i] += taken;
+        for (int k = 0; k < 8; ++k) A.state[k * A.n + ie] = y[k];
+        A.status[ie] = st;
+        A.steps[ie] += taken;
     } else if (st == kActive) {
         for (int32_t k = 0; k < A.n_steps; ++k) {
             if (CKPT && (A.k0 + k) == next_slot * A.ck_every) {
@@ -182,8 +188,9 @@ struct F64Prog {
         if (accept) copy8(L.y, y1);
         return L.st != kActive || L.taken == A.n_steps;
     }
-    __device__ __forceinline__ void store(int64_t i, const Lane &L)
+    __device__ __forceinline__ void store(int64_t item, const Lane &L)
     {
+        const int64_t i = opaque(item);
 #pragma unroll
         for (int k = 0; k < 8; ++k) A.state[k * A.n + i] = L.y[k];
         A.status[i] = L.st;

@@ -27,15 +27,16 @@ using std::fma;
 namespace malbec {
 
 // Reciprocal used by the acceleration.  On the device: FP64 from the hardware
-// estimate refined by two Newton steps, FP32 the hardware reciprocal (1 ulp).
+// estimate r (relative error below 6e-8) refined by one third-order step,
+// r (1 + e + e^2) with e = 1 - x r, which leaves a relative error of order e^3 < 3e-22
+// before the final rounding (within 0.5 ulp, as two Newton steps, one FMA fewer);
+// FP32 the hardware reciprocal (1 ulp).
 MALBEC_HD inline double recip(double x)
 {
 #if defined(__HIP_DEVICE_COMPILE__)
-    double r = __builtin_amdgcn_rcp(x);
-    double e = fma(-x, r, 1.0);
-    r = fma(r, e, r);
-    e = fma(-x, r, 1.0);
-    return fma(r, e, r);
+    const double r = __builtin_amdgcn_rcp(x);
+    const double e = fma(-x, r, 1.0);
+    return fma(r, fma(e, e, e), r);
 #else
     return 1.0 / x;
 #endif

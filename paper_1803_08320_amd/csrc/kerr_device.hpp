@@ -12,6 +12,16 @@ namespace malbec {
 
 enum : int32_t { kActive = 0, kHorizon = 1, kEscape = 2, kDisk = 3, kNonfinite = 4, kBudget = 5 };
 
+// The value x, hidden from the optimiser.  A work item's store computes its
+// addresses from opaque(i): otherwise the compiler keeps the eight per-lane state
+// addresses of the load alive across the whole step loop (16 VGPRs) instead of
+// recomputing them once at the end.
+__device__ __forceinline__ int64_t opaque(int64_t x)
+{
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
 // Per-spacetime constants held in registers or LDS.
 struct Spacetime {
     double M, a, r_stop;  // r_stop = horizon_factor * r_+
@@ -19,40 +29,39 @@ struct Spacetime {
 };
 
 // sin and cos of theta + d from those of theta, for |d| <= kRotMax and
-// |d| <= sin(theta) / 2: Taylor polynomials of sin d (through d^9) and cos d (through
-// d^10), whose truncation is below 3e-18 there, and the angle-addition formulas
-// (about 2 ulp; the second bound keeps sin(theta + d) >= sin(theta) / 2, so the
-// addition does not cancel).
-constexpr double kRotMax = 0.125;
+// |d| <= sin(theta) / 2: Taylor polynomials of sin d (through d^7) and cos d (through
+// d^8), whose truncation is below 2e-17 relative there, and the angle-addition
+// formulas (sin within 4 ulp; the second bound keeps sin(theta + d) >= sin(theta) / 2,
+// so the addition does not cancel; cos is accurate in absolute terms, which is how the
+// right-hand sides use it).  At the step sizes of the workloads (h <= 0.1 with
+// |u^theta| well below 1) stage points stay within 0.04 of the step's start.
+constexpr double kRotMax = 0.04;
 
-// a * b + c as one three-address v_fma_f64.  Used for the polynomial steps below,
-// whose addend is a loop-invariant constant: the compiler's own choice there is the
-// two-address v_fmac_f64 plus a copy of the constant into the destination.
+// a * b + c as one three-address v_fma_f64 with the constant addend c read from a
+// scalar register pair.  Used for the polynomial steps below: the compiler's own
+// choice there is the two-address v_fmac_f64 plus a copy of the constant into the
+// destination, and a constant kept in vector registers costs two VGPRs per lane
+// (or, under register pressure, moves inside the loop).  One scalar source per
+// VOP3 instruction is within the constant-bus limit.
 __device__ __forceinline__ double fma3(double a, double b, double c)
 {
     double r;
-    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
     return r;
 }
 
-// Inverse factorials used by the sin / cos polynomials (Taylor coefficients).
+// Inverse factorials used by the rotation's Taylor polynomials.
 constexpr double kF2 = 1.0 / 2.0, kF3 = 1.0 / 6.0, kF4 = 1.0 / 24.0, kF5 = 1.0 / 120.0,
-                 kF6 = 1.0 / 720.0, kF7 = 1.0 / 5040.0, kF8 = 1.0 / 40320.0, kF9 = 1.0 / 362880.0,
-                 kF10 = 1.0 / 3628800.0, kF11 = 1.0 / 39916800.0, kF12 = 1.0 / 479001600.0,
-                 kF13 = 1.0 / 6227020800.0, kF14 = 1.0 / 87178291200.0,
-                 kF15 = 1.0 / 1307674368000.0, kF16 = 1.0 / 20922789888000.0,
-                 kF17 = 1.0 / 355687428096000.0, kF18 = 1.0 / 6402373705728000.0;
+                 kF6 = 1.0 / 720.0, kF7 = 1.0 / 5040.0, kF8 = 1.0 / 40320.0;
 
 __device__ __forceinline__ void rotate(double s0, double c0, double d, double &s, double &c)
 {
     const double d2 = d * d;
     // sin d = d + d^3 ps(d^2),  cos d = 1 - d^2 pc(d^2)
-    double ps = fma3(d2, kF9, -kF7);
-    ps = fma3(d2, ps, kF5);
+    double ps = fma3(d2, -kF7, kF5);
     ps = fma3(d2, ps, -kF3);
     const double sd = fma(d * d2, ps, d);
-    double pc = fma3(d2, kF10, -kF8);
-    pc = fma3(d2, pc, kF6);
+    double pc = fma3(d2, -kF8, kF6);
     pc = fma3(d2, pc, -kF4);
     pc = fma(d2, pc, kF2);
     const double cd = fma(-d2, pc, 1.0);
@@ -61,8 +70,11 @@ __device__ __forceinline__ void rotate(double s0, double c0, double d, double &s
 }
 
 // Cody-Waite reduction x = theta - k pi/2, k = rint(theta / (pi/2)), with pi/2 split
-// in two parts so that k * kPio2Hi is exact (|k| < 2^20), then the Taylor series of
-// sin x through x^17 and cos x through x^18 on |x| <= pi/4 (truncation below 1e-19).
+// in two parts so that k * kPio2Hi is exact (|k| < 2^20), then minimax polynomials on
+// |x| <= pi/4: sin x = x + x^3 P(x^2) with P of degree 5 and cos x = 1 - x^2 Q(x^2)
+// with Q of degree 6, coefficients from the Remez exchange of gen_minimax.py
+// (relative error of the rounded polynomials below 2.1e-17 and 6e-19; sin and cos
+// measured within 1.5 ulp on gfx950).
 __device__ __forceinline__ double sincos_reduce(double th, double &sx, double &cx)
 {
     constexpr double kPio2Hi = 1.5707963267341256e+00;  // 33 significant bits of pi/2
@@ -71,22 +83,18 @@ __device__ __forceinline__ double sincos_reduce(double th, double &sx, double &c
     const double k = rint(th * k2OverPi);
     const double x = fma(-k, kPio2Lo, fma(-k, kPio2Hi, th));
     const double x2 = x * x;
-    double ps = fma3(x2, kF17, -kF15);
-    ps = fma3(x2, ps, kF13);
-    ps = fma3(x2, ps, -kF11);
-    ps = fma3(x2, ps, kF9);
-    ps = fma3(x2, ps, -kF7);
-    ps = fma3(x2, ps, kF5);
-    ps = fma3(x2, ps, -kF3);
+    double ps = fma3(x2, 1.5918142569704396e-10, -2.5051132049727266e-08);
+    ps = fma3(x2, ps, 2.7557316103657487e-06);
+    ps = fma3(x2, ps, -0.00019841269836761008);
+    ps = fma3(x2, ps, 0.00833333333333095);
+    ps = fma3(x2, ps, -0.16666666666666666);
     sx = fma(x * x2, ps, x);
-    double pc = fma3(x2, kF18, -kF16);
-    pc = fma3(x2, pc, kF14);
-    pc = fma3(x2, pc, -kF12);
-    pc = fma3(x2, pc, kF10);
-    pc = fma3(x2, pc, -kF8);
-    pc = fma3(x2, pc, kF6);
-    pc = fma3(x2, pc, -kF4);
-    pc = fma(x2, pc, kF2);
+    double pc = fma3(x2, 1.1368006029792042e-11, -2.08758868745436e-09);
+    pc = fma3(x2, pc, 2.755731556728916e-07);
+    pc = fma3(x2, pc, -2.480158729369649e-05);
+    pc = fma3(x2, pc, 0.001388888888888078);
+    pc = fma3(x2, pc, -0.04166666666666664);
+    pc = fma(x2, pc, 0.5);
     cx = fma(-x2, pc, 1.0);
     return k;
 }

@@ -184,8 +184,9 @@ struct MixProg {
         }
         return L.st != kActive || L.taken == A.n_steps;
     }
-    __device__ __forceinline__ void store(int64_t i, const Lane &L)
+    __device__ __forceinline__ void store(int64_t item, const Lane &L)
     {
+        const int64_t i = opaque(item);
 #pragma unroll
         for (int k = 0; k < 8; ++k) A.state[k * A.n + i] = (double)L.hi[k] + (double)L.lo[k];
         A.status[i] = L.st;

@@ -115,9 +115,10 @@ struct MonProg {
         }
         return done;
     }
-    __device__ __forceinline__ void store(int64_t i, const Lane &L)
+    __device__ __forceinline__ void store(int64_t item, const Lane &L)
     {
-        base.store(i, L.b);
+        base.store(item, L.b);
+        const int64_t i = opaque(item);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             if (M.reset) M.mon[k * M.n + i] = L.I0[k];
