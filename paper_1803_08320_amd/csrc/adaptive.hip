@@ -34,6 +34,23 @@ struct AdArgs {
     int64_t max_attempts;
 };
 
+// err^(-1/5) for err > 0: a single-precision estimate from the hardware log2 and
+// exp2, then two Newton steps for err y^5 = 1 in FP64, y <- y (6 - err y^5) / 5, each
+// squaring the estimate's relative error (~1e-6 -> 1e-12 -> below rounding).  Outside
+// the single-precision range the estimate is taken at the range's edge; the step-size
+// factor is then clamped to facmin or facmax either way.
+__device__ __forceinline__ double rpow5(double err)
+{
+    const float ef = (float)fmin(fmax(err, 1e-37), 1e37);
+    double y = (double)__builtin_amdgcn_exp2f(-0.2f * __builtin_amdgcn_logf(ef));
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const double y2 = y * y;
+        y = (y * 0.2) * fma(-err, y2 * y2 * y, 6.0);
+    }
+    return y;
+}
+
 struct AdProg {
     const AdArgs &A;
     const Spacetime *table;
@@ -111,7 +128,7 @@ struct AdProg {
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
             const double sc = fma(A.rtol, fmax(fabs(L.y[c]), fabs(y1[c])), A.atol);
-            const double q = e[c] / sc;
+            const double q = e[c] * recip(sc);
             sum = fma(q, q, sum);
         }
         const double err = sqrt(sum * 0.125);
@@ -119,7 +136,7 @@ struct AdProg {
             L.st = kNonfinite;
             return true;
         }
-        const double grow = err > 0.0 ? A.fac * pow(err, -0.2) : A.facmax;
+        const double grow = err > 0.0 ? A.fac * rpow5(err) : A.facmax;
         if (err <= 1.0) {
 #pragma unroll
             for (int c = 0; c < 8; ++c) L.y[c] = y1[c];

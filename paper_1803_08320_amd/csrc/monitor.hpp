@@ -26,7 +26,7 @@ __device__ __forceinline__ void lane_invariants(double M, double a, const double
 {
     const double r = y[1];
     double s, c;
-    sincos(y[2], &s, &c);
+    sincos_any(y[2], s, c);
     const double a2 = a * a, s2 = s * s, r2 = r * r;
     const double rho2 = r2 + a2 * c * c;
     double E, Lz, norm, pth;
@@ -70,15 +70,16 @@ struct MonArgs {
 
 // Base provides the Prog interface plus
 //   static void state64(const Lane&, double y[8])   -- the lane's state in FP64
-//   static int32_t taken(const Lane&)               -- steps taken in this launch
 //   Lane::S                                         -- the lane's Spacetime
+// I_0 and the running maxima stay in the monitor buffer (read and written at the
+// monitored steps only, 96 B per lane every K steps), not in registers.
 template <class Base, bool HAM>
 struct MonProg {
     Base base;
     MonArgs M;
     struct Lane {
         typename Base::Lane b;
-        double I0[4], D[4];
+        int64_t i;     // the lane's index in the batch
         int32_t left;  // steps until the next monitored one
     };
     __device__ __forceinline__ bool load(int64_t i, Lane &L)
@@ -86,18 +87,16 @@ struct MonProg {
         const int32_t s0 = M.steps[i];  // read before the base's store can change it
         if (!base.load(i, L.b)) return false;
         if (M.reset) {
-            double y[8];
+            double y[8], I0[4];
             Base::state64(L.b, y);
-            lane_invariants<HAM>(L.b.S.M, L.b.S.a, y, L.I0);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) L.D[k] = 0.0;
-        } else {
+            lane_invariants<HAM>(L.b.S.M, L.b.S.a, y, I0);
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                L.I0[k] = M.mon[k * M.n + i];
-                L.D[k] = M.mon[(4 + k) * M.n + i];
+                M.mon[k * M.n + i] = I0[k];
+                M.mon[(4 + k) * M.n + i] = 0.0;
             }
         }
+        L.i = i;
         const int32_t r = s0 % M.every;
         L.left = M.every - (r < 0 ? r + M.every : r);
         return true;
@@ -110,21 +109,16 @@ struct MonProg {
             double y[8], I[4];
             Base::state64(L.b, y);
             lane_invariants<HAM>(L.b.S.M, L.b.S.a, y, I);
+            const int64_t i = opaque(L.i);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) L.D[k] = fmax(L.D[k], fabs(I[k] - L.I0[k]));
+            for (int k = 0; k < 4; ++k) {
+                double &D = M.mon[(4 + k) * M.n + i];
+                D = fmax(D, fabs(I[k] - M.mon[k * M.n + i]));
+            }
         }
         return done;
     }
-    __device__ __forceinline__ void store(int64_t item, const Lane &L)
-    {
-        base.store(item, L.b);
-        const int64_t i = opaque(item);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            if (M.reset) M.mon[k * M.n + i] = L.I0[k];
-            M.mon[(4 + k) * M.n + i] = L.D[k];
-        }
-    }
+    __device__ __forceinline__ void store(int64_t item, const Lane &L) { base.store(item, L.b); }
 };
 
 }  // namespace malbec
