@@ -126,7 +126,7 @@ __device__ __forceinline__ void sincos_any(double th, double &s, double &c)
 // evaluation if |d| > kRotMax, or if the step brings theta close to a pole, where the
 // rotation's cancellation would cost relative accuracy in sin theta).
 struct StageTrig {
-    double th0, s0, c0;
+    double th0, s0, c0, lim;
     __device__ __forceinline__ void operator()(int stage, double th, double &s, double &c)
     {
         const double d = th - th0;
@@ -135,7 +135,8 @@ struct StageTrig {
             th0 = th;
             s0 = s;
             c0 = c;
-        } else if (!(fabs(d) <= kRotMax && fabs(d) <= 0.5 * s0)) {
+            lim = fmin(kRotMax, 0.5 * s);
+        } else if (!(fabs(d) <= lim)) {
             sincos_any(th, s, c);
         } else {
             rotate(s0, c0, d, s, c);
