@@ -42,7 +42,7 @@ __device__ __forceinline__ void vjp_accel(double M, double a, double r, double t
 {
     typedef Dual2<double> D;
     double s, c;
-    sincos(th, &s, &c);
+    sincos_any(th, s, c);
     // pass 1: primal coefficients -> contraction -> cotangents of the coefficients
     KerrCoef<double> K;
     kerr_coef<double>(M, a, r, s, c, K);
