@@ -42,8 +42,9 @@ constexpr double kRotMax = 0.04;
 // choice there is the two-address v_fmac_f64 plus a copy of the constant into the
 // destination, and a constant kept in vector registers costs two VGPRs per lane
 // (or, under register pressure, moves inside the loop).  One scalar source per
-// VOP3 instruction is within the constant-bus limit.
-__device__ __forceinline__ double fma3(double a, double b, double c)
+// VOP3 instruction is within the constant-bus limit.  c must be the same in every
+// lane (a literal constant): a scalar register holds one value per wavefront.
+__device__ __forceinline__ double fma3c(double a, double b, double c)
 {
     double r;
     asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
@@ -58,11 +59,11 @@ __device__ __forceinline__ void rotate(double s0, double c0, double d, double &s
 {
     const double d2 = d * d;
     // sin d = d + d^3 ps(d^2),  cos d = 1 - d^2 pc(d^2)
-    double ps = fma3(d2, -kF7, kF5);
-    ps = fma3(d2, ps, -kF3);
+    double ps = fma3c(d2, -kF7, kF5);
+    ps = fma3c(d2, ps, -kF3);
     const double sd = fma(d * d2, ps, d);
-    double pc = fma3(d2, -kF8, kF6);
-    pc = fma3(d2, pc, -kF4);
+    double pc = fma3c(d2, -kF8, kF6);
+    pc = fma3c(d2, pc, -kF4);
     pc = fma(d2, pc, kF2);
     const double cd = fma(-d2, pc, 1.0);
     s = fma(s0, cd, c0 * sd);
@@ -83,17 +84,17 @@ __device__ __forceinline__ double sincos_reduce(double th, double &sx, double &c
     const double k = rint(th * k2OverPi);
     const double x = fma(-k, kPio2Lo, fma(-k, kPio2Hi, th));
     const double x2 = x * x;
-    double ps = fma3(x2, 1.5918142569704396e-10, -2.5051132049727266e-08);
-    ps = fma3(x2, ps, 2.7557316103657487e-06);
-    ps = fma3(x2, ps, -0.00019841269836761008);
-    ps = fma3(x2, ps, 0.00833333333333095);
-    ps = fma3(x2, ps, -0.16666666666666666);
+    double ps = fma3c(x2, 1.5918142569704396e-10, -2.5051132049727266e-08);
+    ps = fma3c(x2, ps, 2.7557316103657487e-06);
+    ps = fma3c(x2, ps, -0.00019841269836761008);
+    ps = fma3c(x2, ps, 0.00833333333333095);
+    ps = fma3c(x2, ps, -0.16666666666666666);
     sx = fma(x * x2, ps, x);
-    double pc = fma3(x2, 1.1368006029792042e-11, -2.08758868745436e-09);
-    pc = fma3(x2, pc, 2.755731556728916e-07);
-    pc = fma3(x2, pc, -2.480158729369649e-05);
-    pc = fma3(x2, pc, 0.001388888888888078);
-    pc = fma3(x2, pc, -0.04166666666666664);
+    double pc = fma3c(x2, 1.1368006029792042e-11, -2.08758868745436e-09);
+    pc = fma3c(x2, pc, 2.755731556728916e-07);
+    pc = fma3c(x2, pc, -2.480158729369649e-05);
+    pc = fma3c(x2, pc, 0.001388888888888078);
+    pc = fma3c(x2, pc, -0.04166666666666664);
     pc = fma(x2, pc, 0.5);
     cx = fma(-x2, pc, 1.0);
     return k;
