@@ -20,7 +20,7 @@ constexpr double kHalfPi = 1.57079632679489661923;  // rounds to the double near
 struct CamArgs {
     Spacetime S;          // M, a, r_stop
     double r_obs, incl, sin_i, cos_i, half_width;
-    double h0, h_r0, r_escape, disk_r_in, disk_r_out;
+    double h0, h_r0, inv_h_r0, r_escape, disk_r_in, disk_r_out;  // inv_h_r0 = RN(1 / h_r0)
     int32_t nx, ny;
     int64_t npix;
     int32_t max_steps;
@@ -60,7 +60,9 @@ __device__ __forceinline__ void pixel_ray(const CamArgs &A, int64_t p, double y[
 __device__ __forceinline__ int32_t camera_step(const CamArgs &A, double y[8], int32_t &n,
                                                double &rc, double &pc)
 {
-    const double h = A.h0 * fmax(1.0, y[1] / A.h_r0);
+    const double q0 = y[1] * A.inv_h_r0;
+    const double q = fma(fma(-A.h_r0, q0, y[1]), A.inv_h_r0, q0);
+    const double h = A.h0 * fmax(1.0, q);
     double y1[8], sr[3];
     rk4_step_f64(A.S, h, y, y1, sr);
     ++n;
@@ -184,6 +186,7 @@ int launch_camera(const malbec_camera &cam, double r_stop, double disk_r_in, int
     A.half_width = cam.half_width;
     A.h0 = cam.h0;
     A.h_r0 = cam.h_r0;
+    A.inv_h_r0 = 1.0 / cam.h_r0;
     A.r_escape = cam.r_escape;
     A.disk_r_in = disk_r_in;
     A.disk_r_out = cam.disk_r_out;
