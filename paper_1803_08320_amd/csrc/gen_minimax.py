@@ -1,16 +1,20 @@
-"""Coefficients of the sin / cos polynomials of kerr_device.hpp (sincos_reduce).
+"""Coefficients of the sin / cos polynomials of kerr_device.hpp (sincos_reduce, FP64)
+and mixed.hip (sincos_f32, FP32).
 
 After the reduction x = theta - k pi/2 the kernels evaluate, on |x| <= pi/4,
-    sin x = x + x^3 P(x^2),   P of degree 5,
-    cos x = 1 - x^2 Q(x^2),   Q of degree 6.
+    sin x = x + x^3 P(x^2),   P of degree 5 (FP64) or 2 (FP32),
+    cos x = 1 - x^2 Q(x^2),   Q of degree 6 (FP64) or 3 (FP32).
 P and Q are the minimax (equi-oscillating) approximations of (sin x - x) / x^3 and
 (1 - cos x) / x^2 as functions of z = x^2 on [0, (pi/4)^2], found with the Remez
 exchange algorithm in 60-digit arithmetic (mpmath).  The script prints the
-coefficients rounded to double, lowest degree first, and the maximum relative error
-of sin and cos with the rounded coefficients (exact arithmetic otherwise).
+coefficients rounded to double (resp. single) precision, lowest degree first, and
+the maximum relative error of sin and cos with the rounded coefficients (exact
+arithmetic otherwise).
 
     python gen_minimax.py
 """
+import struct
+
 import mpmath as mp
 
 mp.mp.dps = 60
@@ -75,21 +79,31 @@ def f_cos(z):
     return (1 - mp.cos(x)) / z
 
 
-def main():
-    P, _ = remez(f_sin, 6)
-    Q, _ = remez(f_cos, 7)
-    Pd = [mp.mpf(float(v)) for v in P]
-    Qd = [mp.mpf(float(v)) for v in Q]
+def to_single(v):
+    return struct.unpack("f", struct.pack("f", float(v)))[0]
+
+
+def report(name, n_sin, n_cos, rnd):
+    P, _ = remez(f_sin, n_sin)
+    Q, _ = remez(f_cos, n_cos)
+    Pr = [mp.mpf(rnd(v)) for v in P]
+    Qr = [mp.mpf(rnd(v)) for v in Q]
     xs = [X * mp.mpf(k) / 3000 for k in range(1, 3001)]
 
     def poly(c, z):
         return sum(c[j] * z ** j for j in range(len(c)))
-    es = max(abs((x + x ** 3 * poly(Pd, x * x) - mp.sin(x)) / mp.sin(x)) for x in xs)
-    ec = max(abs((1 - x * x * poly(Qd, x * x) - mp.cos(x)) / mp.cos(x)) for x in xs)
-    print("P (sin):", ", ".join(repr(float(v)) for v in P))
-    print("Q (cos):", ", ".join(repr(float(v)) for v in Q))
-    print("max relative error with rounded coefficients: sin %s, cos %s"
+    es = max(abs((x + x ** 3 * poly(Pr, x * x) - mp.sin(x)) / mp.sin(x)) for x in xs)
+    ec = max(abs((1 - x * x * poly(Qr, x * x) - mp.cos(x)) / mp.cos(x)) for x in xs)
+    print(name)
+    print("  P (sin):", ", ".join(repr(rnd(v)) for v in P))
+    print("  Q (cos):", ", ".join(repr(rnd(v)) for v in Q))
+    print("  max relative error with rounded coefficients: sin %s, cos %s"
           % (mp.nstr(es, 3), mp.nstr(ec, 3)))
+
+
+def main():
+    report("FP64 (sincos_reduce)", 6, 7, float)
+    report("FP32 (sincos_f32)", 3, 4, to_single)
 
 
 if __name__ == "__main__":

@@ -16,7 +16,27 @@ namespace malbec {
 
 namespace {
 
-// FP32 sin and cos of the stage theta.  Stage 0 takes the library sincosf; later
+// FP32 sin and cos of a moderate theta (stage points, |theta| < 1e3): Cody-Waite
+// reduction by pi/2 in two FMA steps (pi/2 = hi + lo in single precision), minimax
+// polynomials sin x = x + x^3 P(x^2) (P of degree 2) and cos x = 1 - x^2 Q(x^2) (Q of
+// degree 3) on |x| <= pi/4 from gen_minimax.py (relative error 1.3e-8 and 1e-9 with
+// the coefficients rounded to single precision), and the quadrant taken mod 4.
+__device__ __forceinline__ void sincos_f32(float th, float &s, float &c)
+{
+    const float k = rintf(th * 0.636619772f);
+    const float x = fmaf(-k, -4.37113883e-08f, fmaf(-k, 1.57079637f, th));
+    const float z = x * x;
+    const float ps = fmaf(fmaf(z, -1.95880086e-04f, 8.33274890e-03f), z, -1.66666642e-01f);
+    const float sx = fmaf(x * z, ps, x);
+    const float pc = fmaf(fmaf(fmaf(z, -2.44638868e-05f, 1.38875900e-03f), z, -4.16666493e-02f), z, 0.5f);
+    const float cx = fmaf(-z, pc, 1.0f);
+    const int q = ((int)k) & 3;  // k mod 4, negative k too
+    const float ss = (q & 1) ? cx : sx, cc = (q & 1) ? sx : cx;
+    s = (q & 2) ? -ss : ss;
+    c = ((q + 1) & 2) ? -cc : cc;
+}
+
+// FP32 sin and cos of the stage theta.  Stage 0 evaluates them (sincos_f32); later
 // stages rotate that pair by the small angle difference (Taylor terms through d^5 /
 // d^6, truncation below 1e-10 for |d| <= 0.125, far under FP32 rounding).
 struct StageTrigF32 {
@@ -25,7 +45,7 @@ struct StageTrigF32 {
     {
         const float d = th - th0;
         if (stage == 0 || !(fabsf(d) <= 0.125f && fabsf(d) <= 0.5f * s0)) {
-            sincosf(th, &s, &c);
+            sincos_f32(th, s, c);
             if (stage == 0) { th0 = th; s0 = s; c0 = c; }
         } else {
             const float d2 = d * d;
