@@ -233,3 +233,25 @@ def test_checkpoints(m, orc):
         for s in range(N // K + 1):
             want = run_gpu(m, st, s0, 0.02, s * K)[0]
             assert np.array_equal(c[s], want), (chunk, s)
+
+
+@pytest.mark.parametrize("a,r_unstable,r_stable", [(0.0, (4.0, 5.0), (7.0, 10.0)),
+                                                   (0.9, (1.9, 2.1), (3.0, 6.0))])
+def test_unstable_and_stable_circular_orbits(m, orc, a, r_unstable, r_stable):
+    """Sections 4-5: circular orbits inside the ISCO (and outside the photon orbit) are
+    unstable, those outside it stable.  With L perturbed by 1e-8 relative and h = 0.1
+    over 3,000 M, the unstable ones leave r0 (or plunge) and the stable ones stay to
+    the size of the perturbation, on the GPU as in the oracle."""
+    st = [(1.0, a)]
+    rs = r_unstable + r_stable
+    assert max(r_unstable) < orc.r_isco(1.0, a) < min(r_stable)
+    s0 = np.concatenate([orc.ic_circular(7, 1.0, a, 1, r, r, 1e-8) for r in rs], axis=1)
+    got = run_gpu(m, st, s0, 0.1, 30000, horizon_factor=1.0)
+    ref = orc.integrate(st, s0, 0.1, 30000, horizon_factor=1.0)
+    compare(orc, st, s0, *got, *ref, oracle_rerun(orc, st, 0.1, 30000, horizon_factor=1.0))
+    for y, status in ((got[0], got[1]), (ref[0], ref[1])):
+        dep = np.abs(y[1] - s0[1])
+        for i in range(2):
+            assert status[i] != 0 or dep[i] > 0.5, (i, status[i], dep[i])
+        for i in range(2, 4):
+            assert status[i] == 0 and dep[i] < 1e-5 * s0[1, i], (i, status[i], dep[i])
