@@ -265,3 +265,20 @@ def test_flop_count_constant(m, tmp_path):
     assert int(vals["step_flops"]) == m.FLOPS_PER_STEP_F64
     assert int(vals["ham_step_flops"]) == m.FLOPS_PER_STEP_F64_HAM
     assert int(vals["dp45_attempt_flops"]) == m.FLOPS_PER_ATTEMPT_DP45
+
+
+def test_missing_library_and_host_tensors_fail_loudly(m, monkeypatch):
+    """No fallback: without the built library the binding raises, and host tensors are
+    refused before any call (every step runs in the HIP kernels)."""
+    import torch
+    monkeypatch.setattr(m, "LIB_PATH", os.path.join(ROOT, "no_such_dir", "libmalbec.so"))
+    monkeypatch.setattr(m, "_lib", None)
+    with pytest.raises(ImportError):
+        m.lib()
+    monkeypatch.undo()
+    m.lib()
+    state = torch.zeros((8, 4), dtype=torch.float64)
+    status = torch.zeros(4, dtype=torch.int32)
+    steps = torch.zeros(4, dtype=torch.int32)
+    with pytest.raises(ValueError, match="device tensor"):
+        m.integrate(state, status, steps, [(1.0, 0.9)], h=0.02, n_steps=10)
