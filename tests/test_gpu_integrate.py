@@ -255,3 +255,46 @@ def test_unstable_and_stable_circular_orbits(m, orc, a, r_unstable, r_stable):
             assert status[i] != 0 or dep[i] > 0.5, (i, status[i], dep[i])
         for i in range(2, 4):
             assert status[i] == 0 and dep[i] < 1e-5 * s0[1, i], (i, status[i], dep[i])
+
+
+@pytest.mark.parametrize("a", [1.0, 1e-12])
+def test_degenerate_spins(m, orc, a):
+    """The extremal hole a = M (r_+ = M) and a spin just above zero, 700 lanes
+    (ragged), 3,000 steps: parity with the oracle."""
+    st = [(1.0, a)]
+    rc, s0, _, _ = orc.ic_constants(31, st, 700, KERR_RANGES)
+    got = run_gpu(m, st, s0, 0.02, 3000)
+    ref = orc.integrate(st, s0, 0.02, 3000)
+    compare(orc, st, s0, *got, *ref, oracle_rerun(orc, st, 0.02, 3000))
+
+
+def test_largest_batch_indexing(m, orc):
+    """2^24 + 37 lanes (64-bit lane indices, a ragged last block): 40 steps, plain and
+    persistent launches give the same bits; sampled lanes equal the same lanes
+    integrated in a small launch, and lanes holding the oracle's initial data match
+    the oracle."""
+    import torch
+    st = [(1.0, 0.9)]
+    n = (1 << 24) + 37
+    spec = spec_constants(m, 8)
+    state, _, _ = m.init_particles(spec, st, n)
+    idx = np.concatenate([np.arange(0, n, n // 97), np.arange(n - 5, n)])
+    s0 = np.concatenate([orc.ic_constants(8, st, 1, KERR_RANGES, lane0=int(i))[1] for i in idx], axis=1)
+    state[:, torch.as_tensor(idx, device="cuda")] = to_dev(s0, torch.float64)
+    init = state.clone()
+    outs = []
+    for persistent in (False, True):
+        state.copy_(init)
+        status, steps = m.new_lane_arrays(n)
+        m.integrate(state, status, steps, st, h=0.02, n_steps=40, persistent=persistent)
+        torch.cuda.synchronize()
+        outs.append((state[:, idx].cpu().numpy(), status[idx].cpu().numpy(), steps[idx].cpu().numpy(),
+                     float(steps.to(torch.int64).sum().item())))
+    del init
+    for x, y in zip(outs[0], outs[1]):
+        assert np.array_equal(x, y)
+    small = run_gpu(m, st, s0, 0.02, 40)
+    for x, y in zip(outs[0][:3], small):
+        assert np.array_equal(x, y)
+    ref = orc.integrate(st, s0, 0.02, 40)
+    compare(orc, st, s0, *outs[0][:3], *ref, oracle_rerun(orc, st, 0.02, 40))
