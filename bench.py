@@ -87,8 +87,9 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on exactly one GPU (--gpus 1); multi-GPU runs are "
-              "not supported", file=sys.stderr)
+        print("bench.py measures one GPU (--gpus 1): lanes are independent, so a batch split "
+              "over G GPUs runs its 1/G share per GPU (see the shard_1_of_8 leg); runs on "
+              "several GPUs are not supported", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
