@@ -27,6 +27,27 @@ struct RecArgs {
     int32_t n_rec;
 };
 
+__device__ __forceinline__ void copy8(double dst[8], const double src[8])
+{
+#pragma unroll
+    for (int c = 0; c < 8; ++c) dst[c] = src[c];
+}
+
+// One step of either formulation from y into y1; returns the status and sets `accept`
+// (y1 is the lane's state after the step).
+template <bool HAM>
+__device__ __forceinline__ int32_t rec_step(const RecArgs &A, const Spacetime &S,
+                                            const HamConst<double> &P, const double y[8],
+                                            double y1[8], bool &accept)
+{
+    double sr[3];
+    if (HAM)
+        rk4_step_ham_f64(S, P, A.h, y, y1, sr);
+    else
+        rk4_step_f64(S, A.h, y, y1, sr);
+    return terminate_f64(S, A.r_escape, sr, y1, accept);
+}
+
 __device__ __forceinline__ void put_record(const RecArgs &A, int64_t i, int32_t s, double a,
                                            const double y[8], int32_t steps_done)
 {
@@ -63,6 +84,9 @@ __global__ void __launch_bounds__(256) rk4_record_kernel(RecArgs A, StTable T)
         }
     }
     const Spacetime S = MULTI ? lds_st[sid] : T.st[0];
+    // first thread of this wavefront (a scalar); the lane's index is rebuilt from it
+    // at each record, so no per-lane address stays live across the step loop
+    const int32_t wave0 = __builtin_amdgcn_readfirstlane((int32_t)threadIdx.x) & ~63;
     double y[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) y[k] = A.state[k * A.n + i];
@@ -70,26 +94,41 @@ __global__ void __launch_bounds__(256) rk4_record_kernel(RecArgs A, StTable T)
     const int32_t steps0 = A.steps[i];
     int32_t taken = 0;
     for (int32_t s = 0; s < A.n_rec; ++s) {
-        for (int32_t k = 0; k < A.record_every && st == kActive; ++k) {
-            double y1[8], sr[3];
-            if (HAM)
-                rk4_step_ham_f64(S, P, A.h, y, y1, sr);
-            else
-                rk4_step_f64(S, A.h, y, y1, sr);
+        // steps of this record interval, two per iteration with y and y1 swapping
+        // roles (no copy of an accepted step); y holds the state between iterations
+        int32_t left = st == kActive ? A.record_every : 0;
+        double y1[8];
+        bool accept;
+        while (left >= 2) {
             ++taken;
-            bool accept;
-            st = terminate_f64(S, A.r_escape, sr, y1, accept);
-            if (accept) {
-#pragma unroll
-                for (int c = 0; c < 8; ++c) y[c] = y1[c];
+            st = rec_step<HAM>(A, S, P, y, y1, accept);
+            if (st != kActive) {
+                if (accept) copy8(y, y1);
+                break;
             }
+            ++taken;
+            st = rec_step<HAM>(A, S, P, y1, y, accept);
+            if (st != kActive) {
+                if (!accept) copy8(y, y1);
+                break;
+            }
+            left -= 2;
         }
-        put_record(A, i, s, S.a, y, steps0 + taken);
+        if (st == kActive && left == 1) {
+            ++taken;
+            st = rec_step<HAM>(A, S, P, y, y1, accept);
+            if (accept) copy8(y, y1);
+        }
+        const int64_t ie = (int64_t)blockIdx.x * blockDim.x + wave0 +
+                           (int32_t)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+        put_record(A, ie, s, S.a, y, steps0 + taken);
     }
+    const int64_t ie = (int64_t)blockIdx.x * blockDim.x + wave0 +
+                       (int32_t)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
 #pragma unroll
-    for (int k = 0; k < 8; ++k) A.state[k * A.n + i] = y[k];
-    A.status[i] = st;
-    A.steps[i] = steps0 + taken;
+    for (int k = 0; k < 8; ++k) A.state[k * A.n + ie] = y[k];
+    A.status[ie] = st;
+    A.steps[ie] = steps0 + taken;
 }
 
 }  // namespace
