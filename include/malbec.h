@@ -86,6 +86,12 @@ extern "C" {
 #define MALBEC_OP_CAMERA 2
 #define MALBEC_OP_ADJOINT 3
 #define MALBEC_OP_ADAPTIVE 4
+#define MALBEC_OP_ADAPTIVE_ORDER 5
+
+/* Work order of the persistent adaptive kernel (malbec_adaptive.schedule). */
+#define MALBEC_SCHED_INDEX 0      /* lanes in index order */
+#define MALBEC_SCHED_PERIAPSIS 1  /* smallest periapsis first (malbec_adaptive_order) */
+#define MALBEC_SCHED_BUCKETS 1024 /* keys of malbec_adaptive_order: 0 .. 1023 */
 
 /* One Kerr spacetime: mass M > 0 and spin a in [0, M] (Section 2; a > M is a naked
  * singularity and is rejected). */
@@ -158,7 +164,9 @@ typedef struct {
     int32_t block;         /* threads per block, 0 = default */
     int32_t persistent;    /* 1: work-queue kernel (lanes need different attempt counts) */
     int32_t steps_per_chunk; /* persistent: attempts between retire/refill checks, 0 = 8 */
-    int32_t pad_;
+    int32_t schedule;      /* persistent: MALBEC_SCHED_INDEX (0) or MALBEC_SCHED_PERIAPSIS
+                              (hand out the lanes in the order of malbec_adaptive_order);
+                              the results do not depend on it */
 } malbec_adaptive;
 
 /* A stationary, axisymmetric metric in 3+1 form (Section 2, eq. ADM) sampled on a
@@ -204,9 +212,10 @@ MALBEC_API int malbec_version(void);
 
 /* Bytes of caller workspace an operation needs: op = MALBEC_OP_INTEGRATE (n lanes,
  * aux = run->persistent), MALBEC_OP_CAMERA (n = nx * ny pixels), MALBEC_OP_ADJOINT
- * (n lanes, aux = the checkpoint interval K: K * 8 * n doubles) or
- * MALBEC_OP_ADAPTIVE (n lanes, aux = ad->persistent).  Returns 0 for
- * operations that need none. */
+ * (n lanes, aux = the checkpoint interval K: K * 8 * n doubles),
+ * MALBEC_OP_ADAPTIVE (n lanes, aux = ad->persistent ? 1 + ad->schedule : 0; about
+ * 8n bytes with the periapsis schedule) or MALBEC_OP_ADAPTIVE_ORDER (n lanes, aux
+ * unused; about 4n bytes).  Returns 0 for operations that need none. */
 MALBEC_API size_t malbec_workspace_bytes(int32_t op, int64_t n, int32_t aux);
 
 /* Build the initial state of n lanes on the device (one GPU thread per lane).
@@ -319,12 +328,42 @@ MALBEC_API int malbec_invariants(const malbec_batch *b, int64_t n, const double 
  * state: device 8n (in/out); tau, h: device n doubles (in/out: affine parameter and
  * the next step size); status: device n (in/out); steps, rejects: device n int32
  * (accumulate accepted and rejected attempts).  ws: caller workspace of
- * malbec_workspace_bytes(MALBEC_OP_ADAPTIVE, n, ad->persistent) bytes.
+ * malbec_workspace_bytes(MALBEC_OP_ADAPTIVE, n, ad->persistent ? 1 + ad->schedule : 0)
+ * bytes.  ad->schedule = MALBEC_SCHED_PERIAPSIS needs ad->persistent = 1 and n < 2^32;
+ * it changes the order in which lanes are handed out, not their results.
  * Errors: MALBEC_EINVAL, MALBEC_ENOMEM, MALBEC_EDEVICE. */
 MALBEC_API int malbec_integrate_adaptive(const malbec_adaptive *ad, const malbec_batch *b,
                                          int64_t n, double *state, double *tau, double *h,
                                          int32_t *status, int32_t *steps, int32_t *rejects,
                                          void *ws, size_t ws_bytes, void *stream);
+
+/* Work order for the persistent adaptive kernel (ad->schedule = MALBEC_SCHED_PERIAPSIS
+ * computes it in its workspace; this entry point exposes it).  Not an operation of the
+ * paper: a schedule.  An adaptive integrator takes most of its attempts near the
+ * orbit's closest approach, and a long lane handed out last keeps its wavefront busy
+ * after the queue has drained, so the lanes expected to be longest go first.  The
+ * expectation is ranked by the periapsis r_p of the lane's geodesic: the first zero,
+ * inward from the lane's r, of the radial function of Carter's separation (the
+ * constants of motion of Sections 3-4),
+ *   R(r) = [E (r^2 + a^2) - a L_z]^2 - Delta [mu^2 r^2 + (L_z - a E)^2 + Q],
+ * with (E, L_z, Q, mu^2 = -g(u,u)) as malbec_invariants gives them.  key[i] = the
+ * largest j in [1, 1022] with r_j = r_+ 2^(j/32) <= r and R(r_j) < 0, found by a march
+ * inward one bucket at a time from j = floor(32 log2(r / r_+)) (capped at 1022); 0 when
+ * there is none (R(r_+) >= 0 always: the lane plunges, or its forbidden band is
+ * narrower than a bucket; such lanes go first), and MALBEC_SCHED_BUCKETS - 1 = 1023 when
+ * r < 2^(1/32) r_+ or the constants are not finite, and for every lane the integrator
+ * skips (status not ACTIVE, tau >= tau_end, st_of_lane outside 0 .. n_st - 1).
+ * order (device, n uint32, out): a permutation of 0 .. n-1 with key[order[k]]
+ * non-decreasing in k; the order among equal keys is not specified (it may differ
+ * between calls).  keys (device, n uint32, out, nullable): key[i].  state, tau, status:
+ * device, as in malbec_integrate_adaptive (Christoffel form, read only).  ws: caller
+ * workspace of malbec_workspace_bytes(MALBEC_OP_ADAPTIVE_ORDER, n, 0) bytes.  n must be
+ * below 2^32.
+ * Errors: MALBEC_EINVAL, MALBEC_ENOMEM, MALBEC_EDEVICE. */
+MALBEC_API int malbec_adaptive_order(const malbec_batch *b, int64_t n, const double *state,
+                                     const double *tau, const int32_t *status, double tau_end,
+                                     uint32_t *order, uint32_t *keys, void *ws, size_t ws_bytes,
+                                     void *stream);
 
 /* Fill g->nodes (device, written through the pointer passed as `nodes`, which must be
  * g->nodes) with the 3+1 functions of Kerr given in Section 2: alpha =

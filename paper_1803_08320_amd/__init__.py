@@ -24,7 +24,7 @@ __all__ = [
     "ICSpec", "Camera", "init_particles", "integrate", "invariants", "trace_camera",
     "workspace_bytes", "last_error", "version", "lib", "MalbecError", "STATUS", "adjoint",
     "IntegrateFromParams", "convert_state", "integrate_record", "integrate_adaptive",
-    "Grid", "grid_kerr", "integrate_grid",
+    "adaptive_order", "Grid", "grid_kerr", "integrate_grid",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -34,7 +34,8 @@ STATUS = {"ACTIVE": 0, "HORIZON": 1, "ESCAPE": 2, "DISK": 3, "NONFINITE": 4, "BU
 F64, F32_KAHAN = 0, 1
 FORM_CHRISTOFFEL, FORM_HAMILTONIAN = 0, 1
 IC_CANONICAL, IC_CIRCULAR, IC_CONSTANTS, IC_PARAMS = 0, 1, 2, 3
-OP_INTEGRATE, OP_CAMERA, OP_ADJOINT, OP_ADAPTIVE = 1, 2, 3, 4
+OP_INTEGRATE, OP_CAMERA, OP_ADJOINT, OP_ADAPTIVE, OP_ADAPTIVE_ORDER = 1, 2, 3, 4, 5
+SCHED_INDEX, SCHED_PERIAPSIS, SCHED_BUCKETS = 0, 1, 1024
 MAX_SPACETIMES = 64
 
 # Algorithmic FP64 flops of one RK4 step of one lane as implemented (static count of
@@ -95,7 +96,7 @@ class c_adaptive(C.Structure):
                 ("fac", C.c_double), ("facmin", C.c_double), ("facmax", C.c_double),
                 ("max_attempts", C.c_int64), ("horizon_factor", C.c_double),
                 ("r_escape", C.c_double), ("block", C.c_int32), ("persistent", C.c_int32),
-                ("steps_per_chunk", C.c_int32), ("pad_", C.c_int32)]
+                ("steps_per_chunk", C.c_int32), ("schedule", C.c_int32)]
 
 
 class c_grid(C.Structure):
@@ -125,6 +126,9 @@ EXPORTS = {
                                             C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                             C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
                                             C.c_void_p]),
+    "malbec_adaptive_order": (C.c_int, [C.POINTER(c_batch), C.c_int64, C.c_void_p, C.c_void_p,
+                                        C.c_void_p, C.c_double, C.c_void_p, C.c_void_p,
+                                        C.c_void_p, C.c_size_t, C.c_void_p]),
     "malbec_grid_fill_kerr": (C.c_int, [C.POINTER(c_grid), C.c_double, C.c_double, C.c_void_p,
                                         C.c_void_p]),
     "malbec_integrate_grid": (C.c_int, [C.POINTER(c_run), C.POINTER(c_grid), C.c_int64,
@@ -344,14 +348,17 @@ def integrate_adaptive(state: torch.Tensor, tau: torch.Tensor, h: torch.Tensor,
                        max_attempts: int = 1 << 20, horizon_factor: float = 1.01,
                        r_escape: float = 1500.0, block: int = 0, persistent: bool = True,
                        steps_per_chunk: int = 0, st_of_lane: Optional[torch.Tensor] = None,
-                       ws: Optional[torch.Tensor] = None):
+                       ws: Optional[torch.Tensor] = None, schedule: str = "index"):
     """Dormand-Prince 5(4) with per-lane step size up to tau_end; state[8, n], tau and h
-    (float64[n]), status, steps and rejects (int32[n]) in/out."""
+    (float64[n]), status, steps and rejects (int32[n]) in/out.  schedule: "index" or
+    "periapsis" (persistent only: lanes handed out smallest periapsis first; the results
+    are the same)."""
     n = state.shape[-1]
+    sched = {"index": SCHED_INDEX, "periapsis": SCHED_PERIAPSIS}[schedule]
     ad = c_adaptive(tau_end, rtol, atol, fac, facmin, facmax, max_attempts, horizon_factor,
-                    r_escape, block, int(persistent), steps_per_chunk, 0)
+                    r_escape, block, int(persistent), steps_per_chunk, sched)
     b = _Batch(_spacetimes(spacetimes), st_of_lane, n)
-    need = workspace_bytes(OP_ADAPTIVE, n, int(persistent))
+    need = workspace_bytes(OP_ADAPTIVE, n, 1 + sched if persistent else 0)
     if need and ws is None:
         ws = torch.empty(need, dtype=torch.uint8, device=state.device)
     _check(lib().malbec_integrate_adaptive(C.byref(ad), C.byref(b.c), n,
@@ -384,6 +391,25 @@ class Grid:
         _ptr(self.nodes, torch.float64, nr * nth * 5, "nodes")
         return c_grid(nr, nth, self.r0, self.dr, self.th0, self.dth, self.r_stop,
                       self.nodes.data_ptr())
+
+
+
+def adaptive_order(state: torch.Tensor, tau: torch.Tensor, status: torch.Tensor, spacetimes,
+                   tau_end: float, st_of_lane: Optional[torch.Tensor] = None):
+    """The persistent adaptive kernel's periapsis work order: returns (order, keys), both
+    int32[n] on the device holding uint32 values (see malbec_adaptive_order)."""
+    n = state.shape[-1]
+    b = _Batch(_spacetimes(spacetimes), st_of_lane, n)
+    order = torch.empty(n, dtype=torch.int32, device=state.device)
+    keys = torch.empty(n, dtype=torch.int32, device=state.device)
+    need = workspace_bytes(OP_ADAPTIVE_ORDER, n, 0)
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=state.device)
+    _check(lib().malbec_adaptive_order(C.byref(b.c), n,
+                                       _ptr(state, torch.float64, 8 * n, "state"),
+                                       _ptr(tau, torch.float64, n, "tau"),
+                                       _ptr(status, torch.int32, n, "status"), tau_end,
+                                       _ptr(order), _ptr(keys), _ptr(ws), need, _stream()))
+    return order, keys
 
 
 def grid_kerr(M: float, a: float, nr: int, nth: int, r0: float, dr: float, th0: float, dth: float,

@@ -30,6 +30,7 @@ struct AdArgs {
     int32_t *steps;
     int32_t *rejects;
     const int32_t *st_of_lane;
+    const uint32_t *order;  // persistent: lane of work item k (nullptr: k itself)
     double tau_end, rtol, atol, fac, facmin, facmax, r_escape;
     int64_t max_attempts;
 };
@@ -71,8 +72,13 @@ struct AdProg {
         f(0, L.y[1], L.y[2], L.y[4], L.y[5], L.y[6], L.y[7], L.k1.acc[0], L.k1.acc[1], L.k1.acc[2],
           L.k1.acc[3]);
     }
-    __device__ __forceinline__ bool load(int64_t i, Lane &L)
+    __device__ __forceinline__ int64_t lane_of(int64_t item) const
     {
+        return A.order ? (int64_t)A.order[item] : item;
+    }
+    __device__ __forceinline__ bool load(int64_t item, Lane &L)
+    {
+        const int64_t i = lane_of(item);
         L.st = A.status[i];
         if (L.st != kActive) return false;
         int32_t sid = 0;
@@ -154,8 +160,11 @@ struct AdProg {
         }
         return L.st != kActive || !(L.tau < A.tau_end);
     }
-    __device__ __forceinline__ void store(int64_t i, const Lane &L)
+    __device__ __forceinline__ void store(int64_t item, const Lane &L)
     {
+        // the index is laundered so that the addresses of the loads are not kept
+        // live across the attempts for reuse here
+        const int64_t i = lane_of(opaque(item));
 #pragma unroll
         for (int k = 0; k < 8; ++k) A.state[k * A.n + i] = L.y[k];
         A.tau[i] = L.tau;
@@ -198,7 +207,8 @@ __global__ void __launch_bounds__(256) dp45_persistent_kernel(AdArgs A, StTable 
 
 int launch_adaptive(const malbec_adaptive &ad, const StTable &T, const int32_t *st_of_lane,
                     int64_t n, double *state, double *tau, double *h, int32_t *status,
-                    int32_t *steps, int32_t *rejects, void *ws, hipStream_t s)
+                    int32_t *steps, int32_t *rejects, const uint32_t *order, void *ws,
+                    hipStream_t s)
 {
     const int block = ad.block > 0 ? ad.block : 256;
     if (block > 256) return fail(MALBEC_EINVAL, "block %d exceeds the kernel's launch bound 256", block);
@@ -212,6 +222,7 @@ int launch_adaptive(const malbec_adaptive &ad, const StTable &T, const int32_t *
     A.steps = steps;
     A.rejects = rejects;
     A.st_of_lane = multi ? st_of_lane : nullptr;
+    A.order = ad.persistent ? order : nullptr;
     A.tau_end = ad.tau_end;
     A.rtol = ad.rtol;
     A.atol = ad.atol;

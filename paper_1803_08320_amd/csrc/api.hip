@@ -117,8 +117,11 @@ int malbec_version(void) { return 10000 * 0 + 100 * 3 + 0; }
 size_t malbec_workspace_bytes(int32_t op, int64_t n, int32_t aux)
 {
     if (op == MALBEC_OP_CAMERA) return 256;  // work counter (own cache line)
+    if (op == MALBEC_OP_ADAPTIVE && aux == 2 && n >= 0)
+        return 256 + sched_layout(n).bytes;  // work counter, then the periapsis order
     if ((op == MALBEC_OP_INTEGRATE || op == MALBEC_OP_ADAPTIVE) && aux)
         return 256;  // persistent kernel's work counter
+    if (op == MALBEC_OP_ADAPTIVE_ORDER && n > 0) return sched_layout(n).order;
     if (op == MALBEC_OP_ADJOINT && n > 0 && aux > 0) return (size_t)aux * 8 * (size_t)n * sizeof(double);
     return 0;
 }
@@ -323,15 +326,53 @@ int malbec_integrate_adaptive(const malbec_adaptive *ad, const malbec_batch *b, 
         return fail(MALBEC_EINVAL, "block = %d must be a multiple of 64 in [64, 1024] or 0", ad->block);
     if (ad->persistent != 0 && ad->persistent != 1) return fail(MALBEC_EINVAL, "persistent must be 0 or 1");
     if (ad->steps_per_chunk < 0) return fail(MALBEC_EINVAL, "steps_per_chunk < 0");
-    size_t need = malbec_workspace_bytes(MALBEC_OP_ADAPTIVE, n, ad->persistent);
+    if (ad->schedule != MALBEC_SCHED_INDEX && ad->schedule != MALBEC_SCHED_PERIAPSIS)
+        return fail(MALBEC_EINVAL, "unknown schedule %d", ad->schedule);
+    if (ad->schedule == MALBEC_SCHED_PERIAPSIS && !ad->persistent)
+        return fail(MALBEC_EINVAL, "the periapsis schedule needs persistent = 1");
+    if (ad->schedule == MALBEC_SCHED_PERIAPSIS && n > (int64_t)UINT32_MAX)
+        return fail(MALBEC_EINVAL, "the periapsis schedule needs n < 2^32");
+    size_t need = malbec_workspace_bytes(MALBEC_OP_ADAPTIVE, n,
+                                         ad->persistent ? 1 + ad->schedule : 0);
     if (ws_bytes < need || (need > 0 && !ws))
         return fail(MALBEC_ENOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, need);
     StTable T;
     int rc = make_table(b, ad->horizon_factor, 1.0, T);
     if (rc) return rc;
     if (n == 0) return MALBEC_OK;
-    return launch_adaptive(*ad, T, b->st_of_lane, n, state, tau, h, status, steps, rejects, ws,
-                           (hipStream_t)stream);
+    const uint32_t *order = nullptr;
+    if (ad->schedule == MALBEC_SCHED_PERIAPSIS) {
+        // the order sits after the work counter's 256 bytes
+        void *sw = (char *)ws + 256;
+        uint32_t *o = (uint32_t *)((char *)sw + sched_layout(n).order);
+        rc = launch_adaptive_order(T, b->st_of_lane, n, state, tau, status, ad->tau_end, o,
+                                   nullptr, sw, (hipStream_t)stream);
+        if (rc) return rc;
+        order = o;
+    }
+    return launch_adaptive(*ad, T, b->st_of_lane, n, state, tau, h, status, steps, rejects, order,
+                           ws, (hipStream_t)stream);
+}
+
+int malbec_adaptive_order(const malbec_batch *b, int64_t n, const double *state,
+                          const double *tau, const int32_t *status, double tau_end,
+                          uint32_t *order, uint32_t *keys, void *ws, size_t ws_bytes,
+                          void *stream)
+{
+    clear_error();
+    if (n < 0) return fail(MALBEC_EINVAL, "n = %lld < 0", (long long)n);
+    if (n > (int64_t)UINT32_MAX) return fail(MALBEC_EINVAL, "n must be < 2^32");
+    if (n > 0 && (!state || !tau || !status || !order))
+        return fail(MALBEC_EINVAL, "state, tau, status and order must be non-NULL");
+    if (!isfinite(tau_end)) return fail(MALBEC_EINVAL, "tau_end must be finite");
+    size_t need = malbec_workspace_bytes(MALBEC_OP_ADAPTIVE_ORDER, n, 0);
+    if (ws_bytes < need || (need > 0 && !ws))
+        return fail(MALBEC_ENOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, need);
+    StTable T;
+    int rc = make_table(b, 1.0, 1.0, T);
+    if (rc) return rc;
+    return launch_adaptive_order(T, b->st_of_lane, n, state, tau, status, tau_end, order, keys,
+                                 ws, (hipStream_t)stream);
 }
 
 static int check_grid(const malbec_grid *g)

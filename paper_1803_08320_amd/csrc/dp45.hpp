@@ -41,12 +41,19 @@ struct Deriv {
 // stage points 2..6.  accel(stage, r, th, ut, ur, uth, uph, at, ar, ath, aph)
 // evaluates the acceleration at stage point `stage` (1..6 here; 0 is the step's
 // start, whose derivative is k1).
+//
+// Register economy: k1..k3 are kept whole until the fifth stage point is formed; from
+// then on every derivative is folded, as soon as it is known, into running sums of the
+// sixth stage point, of the 5th-order weights (yb) and of the error weights (ee), so
+// at most three derivatives are live at once and none is live at the seventh stage.
+// The operation count is that of the plain weighted sums; only their order differs.
 template <typename T, typename Accel>
 MALBEC_HD inline void dp45_attempt(Accel &accel, T h, const T y[8], const Deriv<T> &k1, T y1[8],
                                    T e[8], Deriv<T> &k7, T sr[5])
 {
     typedef DP45 D;
-    Deriv<T> k2, k3, k4, k5, k6;
+    Deriv<T> k2, k3;
+    T u4[4], a4[4];
     // stage points y + h sum_j a_sj k_j of (r, theta, u); constant weights
     {
         const T r = fma(h * T(D::a21), k1.u[1], y[1]);
@@ -69,55 +76,66 @@ MALBEC_HD inline void dp45_attempt(Accel &accel, T h, const T y[8], const Deriv<
         };
         const T r = fma(h, comb(k1.u[1], k2.u[1], k3.u[1]), y[1]);
         const T th = fma(h, comb(k1.u[2], k2.u[2], k3.u[2]), y[2]);
-        for (int c = 0; c < 4; ++c) k4.u[c] = fma(h, comb(k1.acc[c], k2.acc[c], k3.acc[c]), y[4 + c]);
+        for (int c = 0; c < 4; ++c) u4[c] = fma(h, comb(k1.acc[c], k2.acc[c], k3.acc[c]), y[4 + c]);
         sr[2] = r;
-        accel(3, r, th, k4.u[0], k4.u[1], k4.u[2], k4.u[3], k4.acc[0], k4.acc[1], k4.acc[2], k4.acc[3]);
+        accel(3, r, th, u4[0], u4[1], u4[2], u4[3], a4[0], a4[1], a4[2], a4[3]);
     }
-    {
-        auto comb = [&](const T &x1, const T &x2, const T &x3, const T &x4) {
-            return fma(T(D::a51), x1, fma(T(D::a52), x2, fma(T(D::a53), x3, T(D::a54) * x4)));
-        };
-        const T r = fma(h, comb(k1.u[1], k2.u[1], k3.u[1], k4.u[1]), y[1]);
-        const T th = fma(h, comb(k1.u[2], k2.u[2], k3.u[2], k4.u[2]), y[2]);
-        for (int c = 0; c < 4; ++c)
-            k5.u[c] = fma(h, comb(k1.acc[c], k2.acc[c], k3.acc[c], k4.acc[c]), y[4 + c]);
-        sr[3] = r;
-        accel(4, r, th, k5.u[0], k5.u[1], k5.u[2], k5.u[3], k5.acc[0], k5.acc[1], k5.acc[2], k5.acc[3]);
-    }
-    {
-        auto comb = [&](const T &x1, const T &x2, const T &x3, const T &x4, const T &x5) {
-            return fma(T(D::a61), x1,
-                       fma(T(D::a62), x2, fma(T(D::a63), x3, fma(T(D::a64), x4, T(D::a65) * x5))));
-        };
-        const T r = fma(h, comb(k1.u[1], k2.u[1], k3.u[1], k4.u[1], k5.u[1]), y[1]);
-        const T th = fma(h, comb(k1.u[2], k2.u[2], k3.u[2], k4.u[2], k5.u[2]), y[2]);
-        for (int c = 0; c < 4; ++c)
-            k6.u[c] = fma(h, comb(k1.acc[c], k2.acc[c], k3.acc[c], k4.acc[c], k5.acc[c]), y[4 + c]);
-        sr[4] = r;
-        accel(5, r, th, k6.u[0], k6.u[1], k6.u[2], k6.u[3], k6.acc[0], k6.acc[1], k6.acc[2], k6.acc[3]);
-    }
-    // 5th-order solution (b2 = 0) for all 8 components: x from U, u from A
-    auto bsum = [&](const T &x1, const T &x3, const T &x4, const T &x5, const T &x6) {
-        return fma(T(D::b1), x1, fma(T(D::b3), x3, fma(T(D::b4), x4, fma(T(D::b5), x5, T(D::b6) * x6))));
-    };
-    y1[0] = fma(h, bsum(k1.u[0], k3.u[0], k4.u[0], k5.u[0], k6.u[0]), y[0]);
-    y1[1] = fma(h, bsum(k1.u[1], k3.u[1], k4.u[1], k5.u[1], k6.u[1]), y[1]);
-    y1[2] = fma(h, bsum(k1.u[2], k3.u[2], k4.u[2], k5.u[2], k6.u[2]), y[2]);
-    y1[3] = fma(h, bsum(k1.u[3], k3.u[3], k4.u[3], k5.u[3], k6.u[3]), y[3]);
+    // the fifth stage point, then k1..k4 folded into the running sums
+    T u5[4], a5[4];
+    const T r5 = fma(h, fma(T(D::a51), k1.u[1], fma(T(D::a52), k2.u[1],
+                            fma(T(D::a53), k3.u[1], T(D::a54) * u4[1]))), y[1]);
+    const T th5 = fma(h, fma(T(D::a51), k1.u[2], fma(T(D::a52), k2.u[2],
+                             fma(T(D::a53), k3.u[2], T(D::a54) * u4[2]))), y[2]);
     for (int c = 0; c < 4; ++c)
-        y1[4 + c] = fma(h, bsum(k1.acc[c], k3.acc[c], k4.acc[c], k5.acc[c], k6.acc[c]), y[4 + c]);
+        u5[c] = fma(h, fma(T(D::a51), k1.acc[c], fma(T(D::a52), k2.acc[c],
+                           fma(T(D::a53), k3.acc[c], T(D::a54) * a4[c]))), y[4 + c]);
+    // p6: a_6j-weighted sum over j <= 4 of the six components a stage point needs
+    // (r, theta from U; the four velocities from A); yb, ee: b_j- and e_j-weighted
+    // sums of all eight (b2 = e2 = 0)
+    T p6[6], yb[8], ee[8];
+    {
+        auto six = [&](const Deriv<T> &k, int j) { return j < 2 ? k.u[1 + j] : k.acc[j - 2]; };
+        for (int j = 0; j < 6; ++j) {
+            const T v4 = j < 2 ? u4[1 + j] : a4[j - 2];
+            p6[j] = fma(T(D::a64), v4, fma(T(D::a63), six(k3, j),
+                        fma(T(D::a62), six(k2, j), T(D::a61) * six(k1, j))));
+        }
+        for (int c = 0; c < 8; ++c) {
+            const T v1 = c < 4 ? k1.u[c] : k1.acc[c - 4];
+            const T v3 = c < 4 ? k3.u[c] : k3.acc[c - 4];
+            const T v4 = c < 4 ? u4[c] : a4[c - 4];
+            yb[c] = fma(T(D::b4), v4, fma(T(D::b3), v3, T(D::b1) * v1));
+            ee[c] = fma(T(D::e4), v4, fma(T(D::e3), v3, T(D::e1) * v1));
+        }
+    }
+    sr[3] = r5;
+    accel(4, r5, th5, u5[0], u5[1], u5[2], u5[3], a5[0], a5[1], a5[2], a5[3]);
+    // the sixth stage point; k5 folded
+    T u6[4], a6[4];
+    const T r6 = fma(h, fma(T(D::a65), u5[1], p6[0]), y[1]);
+    const T th6 = fma(h, fma(T(D::a65), u5[2], p6[1]), y[2]);
+    for (int c = 0; c < 4; ++c) u6[c] = fma(h, fma(T(D::a65), a5[c], p6[2 + c]), y[4 + c]);
+    for (int c = 0; c < 8; ++c) {
+        const T v5 = c < 4 ? u5[c] : a5[c - 4];
+        yb[c] = fma(T(D::b5), v5, yb[c]);
+        ee[c] = fma(T(D::e5), v5, ee[c]);
+    }
+    sr[4] = r6;
+    accel(5, r6, th6, u6[0], u6[1], u6[2], u6[3], a6[0], a6[1], a6[2], a6[3]);
+    // 5th-order solution for all 8 components: x from U, u from A
+    for (int c = 0; c < 8; ++c) {
+        const T v6 = c < 4 ? u6[c] : a6[c - 4];
+        y1[c] = fma(h, fma(T(D::b6), v6, yb[c]), y[c]);
+        ee[c] = fma(T(D::e6), v6, ee[c]);
+    }
     // seventh stage at y1 (first same as last)
     for (int c = 0; c < 4; ++c) k7.u[c] = y1[4 + c];
     accel(6, y1[1], y1[2], k7.u[0], k7.u[1], k7.u[2], k7.u[3], k7.acc[0], k7.acc[1], k7.acc[2],
           k7.acc[3]);
-    // error estimate (e2 = 0)
-    auto esum = [&](const T &x1, const T &x3, const T &x4, const T &x5, const T &x6, const T &x7) {
-        return fma(T(D::e1), x1, fma(T(D::e3), x3, fma(T(D::e4), x4, fma(T(D::e5), x5,
-                   fma(T(D::e6), x6, T(D::e7) * x7)))));
-    };
+    // error estimate
     for (int c = 0; c < 4; ++c) {
-        e[c] = h * esum(k1.u[c], k3.u[c], k4.u[c], k5.u[c], k6.u[c], k7.u[c]);
-        e[4 + c] = h * esum(k1.acc[c], k3.acc[c], k4.acc[c], k5.acc[c], k6.acc[c], k7.acc[c]);
+        e[c] = h * fma(T(D::e7), k7.u[c], ee[c]);
+        e[4 + c] = h * fma(T(D::e7), k7.acc[c], ee[4 + c]);
     }
 }
 

@@ -70,9 +70,23 @@ int launch_invariants(const StTable &T, const int32_t *st_of_lane, int64_t n,
                       const double *state, double *out, hipStream_t s);
 int launch_convert(const StTable &T, const int32_t *st_of_lane, int64_t n, double *state,
                    int32_t to_momenta, hipStream_t s);
+// order: the work order of the persistent kernel (nullptr: index order).
 int launch_adaptive(const malbec_adaptive &ad, const StTable &T, const int32_t *st_of_lane,
                     int64_t n, double *state, double *tau, double *h, int32_t *status,
-                    int32_t *steps, int32_t *rejects, void *ws, hipStream_t s);
+                    int32_t *steps, int32_t *rejects, const uint32_t *order, void *ws,
+                    hipStream_t s);
+// Byte offsets in the workspace of the periapsis schedule of n lanes: bucket counts and
+// running offsets (MALBEC_SCHED_BUCKETS uint32 each), keys and order (n uint32 each,
+// 256-byte aligned); `order` is also the size without the order array.
+struct SchedLayout {
+    size_t count, next, key, order, bytes;
+};
+SchedLayout sched_layout(int64_t n);
+// keys: nullptr = in the workspace.
+int launch_adaptive_order(const StTable &T, const int32_t *st_of_lane, int64_t n,
+                          const double *state, const double *tau, const int32_t *status,
+                          double tau_end, uint32_t *order, uint32_t *keys, void *ws,
+                          hipStream_t s);
 int launch_grid_fill_kerr(const malbec_grid &g, double M, double a, double *nodes, hipStream_t s);
 int launch_integrate_grid(const malbec_run &run, const malbec_grid &g, int64_t n, double *state,
                           int32_t *status, int32_t *steps, hipStream_t s);

@@ -50,7 +50,7 @@ def test_struct_layout_matches_header(m, tmp_path):
                    "int main(void){P(malbec_spacetime)P(malbec_batch)P(malbec_ic_spec)"
                    "P(malbec_run)P(malbec_camera)P(malbec_adaptive)O(malbec_adaptive, max_attempts)"
                    "P(malbec_grid)O(malbec_grid, r_stop)O(malbec_grid, nodes)"
-                   "O(malbec_adaptive, steps_per_chunk)O(malbec_ic_spec, rows)O(malbec_ic_spec, max_attempts)"
+                   "O(malbec_adaptive, steps_per_chunk)O(malbec_adaptive, schedule)O(malbec_ic_spec, rows)O(malbec_ic_spec, max_attempts)"
                    "O(malbec_run, checkpoint_every)O(malbec_run, persistent)O(malbec_run, formulation)"
                    "O(malbec_camera, max_steps)O(malbec_camera, persistent)"
                    "O(malbec_batch, st_of_lane)return 0;}\n")
@@ -69,6 +69,7 @@ def test_struct_layout_matches_header(m, tmp_path):
     assert int(got["malbec_grid.nodes"]) == m.c_grid.nodes.offset
     assert int(got["malbec_adaptive.max_attempts"]) == m.c_adaptive.max_attempts.offset
     assert int(got["malbec_adaptive.steps_per_chunk"]) == m.c_adaptive.steps_per_chunk.offset
+    assert int(got["malbec_adaptive.schedule"]) == m.c_adaptive.schedule.offset
     assert int(got["malbec_ic_spec.rows"]) == m.c_ic_spec.rows.offset
     assert int(got["malbec_ic_spec.max_attempts"]) == m.c_ic_spec.max_attempts.offset
     assert int(got["malbec_run.checkpoint_every"]) == m.c_run.checkpoint_every.offset
@@ -213,7 +214,7 @@ def test_init_and_camera_argument_errors(m):
 def _adaptive(m, **kw):
     d = dict(tau_end=10.0, rtol=1e-9, atol=1e-9, fac=0.9, facmin=0.2, facmax=5.0,
              max_attempts=100, horizon_factor=1.01, r_escape=1500.0, block=0, persistent=0,
-             steps_per_chunk=0, pad_=0)
+             steps_per_chunk=0, schedule=0)
     d.update(kw)
     return m.c_adaptive(**d)
 
@@ -222,7 +223,8 @@ def _adaptive(m, **kw):
     (dict(rtol=0.0), -1), (dict(atol=-1.0), -1), (dict(fac=1.5), -1), (dict(facmin=0.0), -1),
     (dict(facmax=0.5), -1), (dict(max_attempts=0), -1), (dict(tau_end=float("inf")), -1),
     (dict(block=100), -1), (dict(persistent=3), -1), (dict(persistent=1), -2),
-    (dict(horizon_factor=0.5), -1),
+    (dict(horizon_factor=0.5), -1), (dict(schedule=2), -1), (dict(schedule=-1), -1),
+    (dict(schedule=1), -1), (dict(persistent=1, schedule=1), -2),
 ])
 def test_adaptive_argument_errors(m, kw, expect):
     ad = _adaptive(m, **kw)
@@ -231,6 +233,29 @@ def test_adaptive_argument_errors(m, kw, expect):
                                            FAKE, FAKE, None, 0, None)
     assert rc == expect, m.last_error()
     assert m.workspace_bytes(m.OP_ADAPTIVE, 10, 1) >= 8
+
+
+def test_adaptive_order_workspace_and_argument_errors(m):
+    """Workspace of the periapsis schedule (bucket counts and offsets, keys, order) and the
+    argument checks of malbec_adaptive_order, none of which touches the device."""
+    rnd = lambda x: (x + 255) // 256 * 256
+    for n in (1, 255, 1000, 1 << 20):
+        assert m.workspace_bytes(m.OP_ADAPTIVE_ORDER, n, 0) == 2 * 4 * m.SCHED_BUCKETS + rnd(4 * n)
+        assert m.workspace_bytes(m.OP_ADAPTIVE, n, 2) == (256 + 2 * 4 * m.SCHED_BUCKETS + rnd(4 * n)
+                                                           + 4 * n)
+        assert m.workspace_bytes(m.OP_ADAPTIVE, n, 1) == 256
+    assert m.workspace_bytes(m.OP_ADAPTIVE_ORDER, 0, 0) == 0
+    arr, b = _batch(m)
+    order = m.lib().malbec_adaptive_order
+    big = 1 << 30
+    assert order(C.byref(b), -1, FAKE, FAKE, FAKE, 10.0, FAKE, None, FAKE, big, None) == -1
+    assert order(C.byref(b), 1 << 32, FAKE, FAKE, FAKE, 10.0, FAKE, None, FAKE, big, None) == -1
+    assert order(C.byref(b), 4, FAKE, FAKE, FAKE, 10.0, None, None, FAKE, big, None) == -1
+    assert order(C.byref(b), 4, None, FAKE, FAKE, 10.0, FAKE, None, FAKE, big, None) == -1
+    assert order(C.byref(b), 4, FAKE, FAKE, FAKE, float("nan"), FAKE, None, FAKE, big, None) == -1
+    assert order(C.byref(b), 4, FAKE, FAKE, FAKE, 10.0, FAKE, None, FAKE, 100, None) == -2
+    assert order(C.byref(b), 4, FAKE, FAKE, FAKE, 10.0, FAKE, None, None, big, None) == -2
+    assert order(C.byref(b), 0, None, None, None, 10.0, None, None, None, 0, None) == 0
 
 
 @pytest.mark.parametrize("kw,run_kw,expect", [

@@ -132,7 +132,7 @@ def test_persistent_equals_plain_bitwise_and_budget(m, orc):
 
 def test_adaptive_full_size_sampled(m, orc):
     """The benchmark's adaptive launch: Kerr a = 0.9, 1,048,576 lanes to tau = 400 at
-    rtol = atol = 1e-12 under the persistent queue.  256 strided lanes hold the
+    rtol = atol = 1e-12 under the persistent queue in periapsis order.  256 strided lanes hold the
     oracle's own initial data (the device builder's agree with it to the rounding of
     sqrt(R)) and are compared with the oracle; over all lanes, active ones end on
     tau_end."""
@@ -153,7 +153,7 @@ def test_adaptive_full_size_sampled(m, orc):
     steps = torch.zeros(n, dtype=torch.int32, device="cuda")
     rej = torch.zeros(n, dtype=torch.int32, device="cuda")
     m.integrate_adaptive(state, tau, h, status, steps, rej, st, 400.0, rtol=1e-12, atol=1e-12,
-                         persistent=True)
+                         persistent=True, schedule="periapsis")
     torch.cuda.synchronize()
     all_out = tuple(x.cpu().numpy() for x in (state, tau, h, status, steps, rej))
     got = tuple(x[..., idx] for x in all_out)
@@ -181,3 +181,121 @@ def test_adaptive_full_size_sampled(m, orc):
     assert np.all(np.abs(g[0] - ref[1])[bud] <= 3e-5 * ref[1][bud])
     assert np.all(np.abs(g[1] - ref[2])[bud] <= 1e-3 * ref[2][bud])
     assert np.median(np.abs(g[0] - ref[1])[bud] / ref[1][bud]) <= 1e-6
+
+
+def run_lanes(m, sts, s0, status, tau0, tau_end, st_of_lane=None, **kw):
+    import torch
+    n = s0.shape[1]
+    out = [to_dev(s0, torch.float64), to_dev(tau0, torch.float64),
+           torch.full((n,), 0.1, dtype=torch.float64, device="cuda"), to_dev(status, torch.int32),
+           torch.zeros(n, dtype=torch.int32, device="cuda"),
+           torch.zeros(n, dtype=torch.int32, device="cuda")]
+    sol = None if st_of_lane is None else to_dev(st_of_lane, torch.int32)
+    args = dict(CTL)
+    args.update(kw)
+    m.integrate_adaptive(*out, sts, tau_end, st_of_lane=sol, **args)
+    torch.cuda.synchronize()
+    return tuple(x.cpu().numpy() for x in out)
+
+
+def skipped_lanes(n, sol=None):
+    """Lanes the integrator does not load: not ACTIVE, tau already at tau_end, or a bad
+    spacetime index."""
+    status = np.zeros(n, np.int32)
+    status[3::97] = 1
+    status[7::101] = 4
+    tau0 = np.zeros(n)
+    tau0[5::89] = 500.0
+    if sol is not None:
+        sol = sol.copy()
+        sol[11::103] = 7
+    return status, tau0, sol
+
+
+def test_periapsis_schedule_gives_the_same_results(m, orc):
+    """The periapsis order changes when lanes are handed out, not what they compute: the
+    results are bitwise those of the index order and of the plain kernel, on three spins
+    in one launch with inactive lanes, lanes already at tau_end, lanes with a bad
+    spacetime index, plunging lanes, and a ragged tail."""
+    sts = [(1.0, 0.0), (1.0, 0.5), (1.0, 0.9)]
+    n = 3001
+    sol = (np.arange(n) % 3).astype(np.int32)
+    rc, s0, _, _ = orc.ic_constants(91, sts, n, KERR_RANGES, st_of_lane=sol)
+    status, tau0, sol = skipped_lanes(n, sol)
+    a = run_lanes(m, sts, s0, status, tau0, 300.0, sol, persistent=True, schedule="index")
+    b = run_lanes(m, sts, s0, status, tau0, 300.0, sol, persistent=True, schedule="periapsis",
+                  steps_per_chunk=5)
+    c = run_lanes(m, sts, s0, status, tau0, 300.0, sol, persistent=False)
+    for x, y, z in zip(a, b, c):
+        assert np.array_equal(x, y) and np.array_equal(x, z)
+    st = a[3]
+    assert (st == 1).sum() > 30 and np.all(st[11::103][status[11::103] == 0] == 4)
+    assert np.array_equal(a[0][:, 5::89], s0[:, 5::89])
+
+
+def periapsis_key(M, a, E, L, Q, mu2, r0, status, tau0, tau_end):
+    """The key of malbec_adaptive_order written out: the bucket j of the first zero of
+    Carter's radial function R inward from r0 on r_j = r_+ 2^(j/32)."""
+    if status != 0 or not tau0 < tau_end:
+        return 1023
+    rp = M + math.sqrt(M * M - a * a)
+
+    def neg(j):
+        r = rp * 2.0 ** (j / 32.0)
+        D = r * r - 2 * M * r + a * a
+        P = E * (r * r + a * a) - a * L
+        return P * P - D * (mu2 * r * r + (L - a * E) ** 2 + Q) < 0.0
+    x = 32.0 * math.log2(r0 / rp)
+    if not x >= 1.0:
+        return 1023
+    j = int(min(x, 1022.0))
+    while j > 0 and not neg(j):
+        j -= 1
+    return j
+
+
+def test_periapsis_order_is_a_sorted_permutation(m, orc):
+    """malbec_adaptive_order on 5,003 Kerr lanes: a permutation of the lanes whose keys
+    do not decrease; skipped lanes take the last key; the keys are the periapsis
+    buckets computed here from the oracle's constants of the same states (a key decided
+    by the sign of R at a grid point may differ where R is within rounding of zero)."""
+    import torch
+    M, a = 1.0, 0.9
+    sts = [(M, a)]
+    n = 5003
+    rc, s0, _, _ = orc.ic_constants(92, sts, n, KERR_RANGES)
+    status, tau0, _ = skipped_lanes(n)
+    order, keys = m.adaptive_order(to_dev(s0, torch.float64), to_dev(tau0, torch.float64),
+                                   to_dev(status, torch.int32), sts, 400.0)
+    o = order.cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+    k = keys.cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+    assert np.array_equal(np.sort(o), np.arange(n))
+    assert np.all(np.diff(k[o]) >= 0)
+    inv = orc.invariants(sts, s0)
+    want = np.array([periapsis_key(M, a, inv[0, i], inv[1, i], inv[2, i], -inv[3, i], s0[1, i],
+                                   status[i], tau0[i], 400.0) for i in range(n)])
+    skip = (status != 0) | (tau0 >= 400.0)
+    assert np.all(k[skip] == 1023) and skip.sum() > 100
+    agree = k == want
+    assert agree.mean() >= 0.999, np.flatnonzero(~agree)[:10]
+    # a bound lane's periapsis lies inside its radius
+    bound = (k > 0) & (k < 1023) & ~skip
+    assert bound.mean() > 0.5
+    rp = M + math.sqrt(M * M - a * a)
+    assert np.all(rp * 2.0 ** (k[bound] / 32.0) <= s0[1][bound])
+
+
+def test_periapsis_key_of_circular_orbits(m, orc):
+    """On an equatorial circular orbit R has a double zero at the orbit's radius (R =
+    R' = 0 there, Sections 3-4), so the periapsis is r0 itself: the key is the bucket
+    that holds r0 or the one below it."""
+    import torch
+    M, a = 1.0, 0.9
+    s0 = orc.ic_circular(93, M, a, 257, 4.0, 40.0, 0.0)
+    n = s0.shape[1]
+    z = np.zeros(n)
+    order, keys = m.adaptive_order(to_dev(s0, torch.float64), to_dev(z, torch.float64),
+                                   to_dev(np.zeros(n, np.int32), torch.int32), [(M, a)], 10.0)
+    k = keys.cpu().numpy().astype(np.int64)
+    j0 = np.floor(32.0 * np.log2(s0[1] / (M + math.sqrt(M * M - a * a)))).astype(np.int64)
+    assert np.all((k == j0) | (k == j0 - 1)), np.c_[k, j0][k - j0 < -1][:5]
