@@ -12,7 +12,9 @@
 //
 // Lanes need different numbers of attempts, so the work-queue driver of
 // persistent.hpp (one attempt per "step") keeps the wavefronts full; a
-// one-thread-per-lane kernel gives the same bits.
+// one-thread-per-lane kernel gives the same bits.  The queue hands out work item k as
+// lane order[k] when a work order is given (schedule.hip: smallest periapsis, i.e.
+// longest expected lane, first), else lane k.
 #include "dp45.hpp"
 #include "internal.hpp"
 #include "persistent.hpp"
