@@ -492,21 +492,24 @@ def main():
         m.convert_state(z0, st, True)
         ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
 
-        def run_grid(record):
+        def run_grid(record, grid):
             state.copy_(z0)
             status.zero_()
             steps.zero_()
             if record:
                 ev[0].record()
-            m.integrate_grid(state, status, steps, g, h, n_g, 55.0, block=args.block)
+            m.integrate_grid(state, status, steps, grid, h, n_g, 55.0, block=args.block)
             if record:
                 ev[1].record()
-        run_grid(False)
+        run_grid(False, g)
         torch.cuda.synchronize()
-        run_grid(True)
+        run_grid(True, g)
         torch.cuda.synchronize()
         dt = ev[0].elapsed_time(ev[1]) / 1e3
         ls = int(steps.sum().item())
+        end64 = state.clone()
+        st64 = status.clone()
+        act64 = st64 == 0
         result["grid_3p1"] = {
             "value": ls / dt, "unit": "lane-steps/s", "grid": [801, 401],
             "rk4_steps": n_g, "kernel_ms": 1e3 * dt,
@@ -515,6 +518,29 @@ def main():
             "gathered_bytes_per_lane_step": 4 * 16 * 40,
             "gather_GB_per_s": 4 * 16 * 40 * ls / dt / 1e9,
             "active_frac": float((status == 0).float().mean().item())}
+        # the same grid with its node values stored in single precision (half the
+        # gathered bytes; arithmetic in FP64), and how far its orbits end from the
+        # double-precision grid's
+        g32 = m.grid_kerr(1.0, 0.9, 801, 401, 1.5, 60.0 / 800, 0.1, (math.pi - 0.2) / 400,
+                          1.2 * (1.0 + math.sqrt(1.0 - 0.81)), node_dtype=torch.float32)
+        run_grid(False, g32)
+        torch.cuda.synchronize()
+        run_grid(True, g32)
+        torch.cuda.synchronize()
+        dt32 = ev[0].elapsed_time(ev[1]) / 1e3
+        ls32 = int(steps.sum().item())
+        both = act64 & (status == 0)
+        dpos = ((state[1:4] - end64[1:4]).abs() / end64[1:4].abs().clamp(min=1.0)).amax(dim=0)
+        dpos = dpos[both].cpu().numpy()
+        result["grid_3p1"]["node_f32"] = {
+            "value": ls32 / dt32, "unit": "lane-steps/s", "kernel_ms": 1e3 * dt32,
+            "speedup_vs_f64_nodes": (ls32 / dt32) / (ls / dt),
+            "gathered_bytes_per_lane_step": 4 * 16 * 20,
+            "gather_GB_per_s": 4 * 16 * 20 * ls32 / dt32 / 1e9,
+            "pos_diff_vs_f64_nodes_p50": float(np.quantile(dpos, 0.5)),
+            "pos_diff_vs_f64_nodes_p99": float(np.quantile(dpos, 0.99)),
+            "status_agree_frac": float((status == st64).float().mean().item())}
+        del g32, end64, st64
 
     if not args.no_extra:
         result["extra"] = extra_legs(m, torch, np)

@@ -169,17 +169,26 @@ typedef struct {
                               the results do not depend on it */
 } malbec_adaptive;
 
+/* Storage of the node values of a malbec_grid (the interpolation and every other
+ * operation run in FP64 either way). */
+#define MALBEC_GRID_F64 0 /* double */
+#define MALBEC_GRID_F32 1 /* float: half the bytes gathered per right-hand side, which
+                             set the gridded kernel's rate, at a rounding of the stored
+                             functions of 2^-24 relative */
+
 /* A stationary, axisymmetric metric in 3+1 form (Section 2, eq. ADM) sampled on a
  * uniform (r, theta) grid: shift beta = (0, 0, beta^phi), diagonal spatial metric.
- * Node (i, j) sits at r = r0 + i dr, theta = th0 + j dth and holds five doubles,
+ * Node (i, j) sits at r = r0 + i dr, theta = th0 + j dth and holds five values,
  * nodes[(i * nth + j) * 5 + k], k = (alpha, beta^phi, gamma_rr, gamma_thth,
- * gamma_phph / sin^2 theta). */
+ * gamma_phph / sin^2 theta), stored as node_precision says. */
 typedef struct {
-    int32_t nr, nth;     /* nodes in r and theta, >= 4 each */
-    double r0, dr;       /* dr > 0 */
-    double th0, dth;     /* dth > 0; th0 > 0 and th0 + (nth - 1) dth < pi */
-    double r_stop;       /* lanes stop at r <= r_stop (e.g. 1.01 r_+); >= r0 + dr */
-    const double *nodes; /* device, nr * nth * 5 doubles */
+    int32_t nr, nth;        /* nodes in r and theta, >= 4 each */
+    double r0, dr;          /* dr > 0 */
+    double th0, dth;        /* dth > 0; th0 > 0 and th0 + (nth - 1) dth < pi */
+    double r_stop;          /* lanes stop at r <= r_stop (e.g. 1.01 r_+); >= r0 + dr */
+    const void *nodes;      /* device, nr * nth * 5 doubles or floats */
+    int32_t node_precision; /* MALBEC_GRID_F64 (0) or MALBEC_GRID_F32 (1) */
+    int32_t pad_;
 } malbec_grid;
 
 /* Camera (malbec_trace_camera): Bardeen image plane of a static observer at
@@ -366,11 +375,12 @@ MALBEC_API int malbec_adaptive_order(const malbec_batch *b, int64_t n, const dou
                                      void *stream);
 
 /* Fill g->nodes (device, written through the pointer passed as `nodes`, which must be
- * g->nodes) with the 3+1 functions of Kerr given in Section 2: alpha =
+ * g->nodes, in g->node_precision's type: each value computed in FP64, then rounded
+ * to nearest) with the 3+1 functions of Kerr given in Section 2: alpha =
  * sqrt(rho^2 Delta / Sigma), beta^phi = -2 M a r / Sigma, gamma_rr = rho^2 / Delta,
  * gamma_thth = rho^2, gamma_phph / sin^2 theta = Sigma / rho^2 (the test metric of the
  * gridded path).  Errors: MALBEC_EINVAL, MALBEC_EDEVICE. */
-MALBEC_API int malbec_grid_fill_kerr(const malbec_grid *g, double M, double a, double *nodes,
+MALBEC_API int malbec_grid_fill_kerr(const malbec_grid *g, double M, double a, void *nodes,
                                      void *stream);
 
 /* Fixed-step RK4 of Hamilton's equations (Section 2, eq. Ham) in the gridded 3+1

@@ -36,6 +36,7 @@ FORM_CHRISTOFFEL, FORM_HAMILTONIAN = 0, 1
 IC_CANONICAL, IC_CIRCULAR, IC_CONSTANTS, IC_PARAMS = 0, 1, 2, 3
 OP_INTEGRATE, OP_CAMERA, OP_ADJOINT, OP_ADAPTIVE, OP_ADAPTIVE_ORDER = 1, 2, 3, 4, 5
 SCHED_INDEX, SCHED_PERIAPSIS, SCHED_BUCKETS = 0, 1, 1024
+GRID_F64, GRID_F32 = 0, 1
 MAX_SPACETIMES = 64
 
 # Algorithmic FP64 flops of one RK4 step of one lane as implemented (static count of
@@ -102,7 +103,7 @@ class c_adaptive(C.Structure):
 class c_grid(C.Structure):
     _fields_ = [("nr", C.c_int32), ("nth", C.c_int32), ("r0", C.c_double), ("dr", C.c_double),
                 ("th0", C.c_double), ("dth", C.c_double), ("r_stop", C.c_double),
-                ("nodes", C.c_void_p)]
+                ("nodes", C.c_void_p), ("node_precision", C.c_int32), ("pad_", C.c_int32)]
 
 
 EXPORTS = {
@@ -375,8 +376,9 @@ def integrate_adaptive(state: torch.Tensor, tau: torch.Tensor, h: torch.Tensor,
 @dataclass
 class Grid:
     """A 3+1 metric on a uniform (r, theta) grid (include/malbec.h, malbec_grid):
-    nodes is a device float64 tensor [nr, nth, 5] of (alpha, beta^phi, gamma_rr,
-    gamma_thth, gamma_phph / sin^2 theta)."""
+    nodes is a device tensor [nr, nth, 5] of (alpha, beta^phi, gamma_rr, gamma_thth,
+    gamma_phph / sin^2 theta), float64 or float32 (MALBEC_GRID_F32: half the gathered
+    bytes; the arithmetic stays FP64)."""
     nodes: torch.Tensor
     r0: float
     dr: float
@@ -388,9 +390,12 @@ class Grid:
         nr, nth, k = self.nodes.shape
         if k != 5:
             raise ValueError("nodes must have shape [nr, nth, 5]")
-        _ptr(self.nodes, torch.float64, nr * nth * 5, "nodes")
+        prec = {torch.float64: GRID_F64, torch.float32: GRID_F32}.get(self.nodes.dtype)
+        if prec is None:
+            raise ValueError("nodes must be float64 or float32")
+        _ptr(self.nodes, self.nodes.dtype, nr * nth * 5, "nodes")
         return c_grid(nr, nth, self.r0, self.dr, self.th0, self.dth, self.r_stop,
-                      self.nodes.data_ptr())
+                      self.nodes.data_ptr(), prec, 0)
 
 
 
@@ -413,9 +418,10 @@ def adaptive_order(state: torch.Tensor, tau: torch.Tensor, status: torch.Tensor,
 
 
 def grid_kerr(M: float, a: float, nr: int, nth: int, r0: float, dr: float, th0: float, dth: float,
-              r_stop: float) -> Grid:
-    """A grid filled on the device with Kerr's 3+1 functions (Section 2)."""
-    g = Grid(torch.empty((nr, nth, 5), dtype=torch.float64, device="cuda"), r0, dr, th0, dth,
+              r_stop: float, node_dtype=torch.float64) -> Grid:
+    """A grid filled on the device with Kerr's 3+1 functions (Section 2), node values
+    stored as node_dtype (float64 or float32)."""
+    g = Grid(torch.empty((nr, nth, 5), dtype=node_dtype, device="cuda"), r0, dr, th0, dth,
              r_stop)
     cg = g.to_c()
     _check(lib().malbec_grid_fill_kerr(C.byref(cg), M, a, C.c_void_p(g.nodes.data_ptr()),

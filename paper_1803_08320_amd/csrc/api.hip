@@ -382,6 +382,8 @@ static int check_grid(const malbec_grid *g)
     if ((int64_t)g->nr * g->nth > ((int64_t)1 << 31))
         return fail(MALBEC_EINVAL, "grid too large");
     if (!g->nodes) return fail(MALBEC_EINVAL, "grid nodes are NULL");
+    if (g->node_precision != MALBEC_GRID_F64 && g->node_precision != MALBEC_GRID_F32)
+        return fail(MALBEC_EINVAL, "unknown node_precision %d", g->node_precision);
     if (!(g->dr > 0.0) || !(g->dth > 0.0) || !isfinite(g->r0) || !isfinite(g->dr) ||
         !isfinite(g->th0) || !isfinite(g->dth))
         return fail(MALBEC_EINVAL, "need finite r0, th0 and dr, dth > 0");
@@ -392,7 +394,7 @@ static int check_grid(const malbec_grid *g)
     return MALBEC_OK;
 }
 
-int malbec_grid_fill_kerr(const malbec_grid *g, double M, double a, double *nodes, void *stream)
+int malbec_grid_fill_kerr(const malbec_grid *g, double M, double a, void *nodes, void *stream)
 {
     clear_error();
     int rc = check_grid(g);

@@ -5,7 +5,8 @@
 // the route to numerically computed metrics.  Here a stationary, axisymmetric metric
 // with beta = (0, 0, beta^phi) and diagonal gamma is five functions of (r, theta),
 //   F = (alpha, beta^phi, gamma_rr, gamma_thth, gamma_phph / sin^2 theta),
-// sampled on a uniform grid (node (i, j) holds its five values contiguously, 40 B).
+// sampled on a uniform grid (node (i, j) holds its five values contiguously: 40 B as
+// doubles, 20 B as floats; the values are widened to FP64 on load).
 // At a point the kernel takes the tensor product of 4-point Lagrange interpolants
 // (16 nodes: four rows of four consecutive nodes, 160 contiguous bytes each), the
 // derivatives of that interpolant, the inverse metric
@@ -13,8 +14,9 @@
 //   g^phph = 1/gamma_phph - (beta^phi)^2/alpha^2, g^rr = 1/gamma_rr, g^thth = 1/gamma_thth
 // and its r, theta derivatives, and Hamilton's equations (eq. Ham) on (x^mu, p_mu)
 // with classic RK4 (p_t and p_phi are constants).  Each right-hand side gathers
-// 640 B of grid data, read from the caches (the grid is small next to L2 + MALL);
-// the work per lane-step is ~4 x (interpolation 220 fma + metric algebra).
+// 640 B of grid data (320 B as floats), read from the caches (the grid is small next
+// to L2 + MALL); those gathers, not the work per lane-step (~4 x (interpolation
+// 220 fma + metric algebra)), set the rate.
 #include "internal.hpp"
 
 namespace malbec {
@@ -26,7 +28,7 @@ struct GridArgs {
     double *state;
     int32_t *status;
     int32_t *steps;
-    const double *nodes;
+    const void *nodes;  // Node[nr * nth * 5], Node = double or float
     int32_t nr, nth;
     double r0, idr, th0, idth;   // inverse spacings
     double rlo, rhi, tlo, thi;   // interior (stencils and stage points stay inside)
@@ -60,6 +62,7 @@ __device__ __forceinline__ int32_t cell(double x, double x0, double ih, int32_t 
 }
 
 // F, dF/dr, dF/dtheta of the five functions at (r, theta).
+template <typename Node>
 __device__ __forceinline__ void grid_eval(const GridArgs &A, double r, double th, double F[5],
                                           double Fr[5], double Ft[5])
 {
@@ -70,10 +73,10 @@ __device__ __forceinline__ void grid_eval(const GridArgs &A, double r, double th
     lagrange4(ut, wt, dwt);
 #pragma unroll
     for (int k = 0; k < 5; ++k) { F[k] = 0.0; Fr[k] = 0.0; Ft[k] = 0.0; }
-    // one stencil row (4 nodes, 160 contiguous bytes) in flight at a time
+    // one stencil row (4 nodes, 160 or 80 contiguous bytes) in flight at a time
 #pragma unroll 1
     for (int a = 0; a < 4; ++a) {
-        const double *row = A.nodes + ((int64_t)(i - 1 + a) * A.nth + (j - 1)) * 5;
+        const Node *row = (const Node *)A.nodes + ((int64_t)(i - 1 + a) * A.nth + (j - 1)) * 5;
         double v[5], vt[5];
 #pragma unroll
         for (int k = 0; k < 5; ++k) { v[k] = 0.0; vt[k] = 0.0; }
@@ -81,7 +84,7 @@ __device__ __forceinline__ void grid_eval(const GridArgs &A, double r, double th
         for (int b = 0; b < 4; ++b) {
 #pragma unroll
             for (int k = 0; k < 5; ++k) {
-                const double f = row[b * 5 + k];
+                const double f = (double)row[b * 5 + k];
                 v[k] = fma(wt[b], f, v[k]);
                 vt[k] = fma(dwt[b], f, vt[k]);
             }
@@ -98,6 +101,7 @@ __device__ __forceinline__ void grid_eval(const GridArgs &A, double r, double th
 }
 
 // Canonical right-hand side with the gridded metric; records the stage point.
+template <typename Node>
 struct GridHam {
     const GridArgs &A;
     const HamConst<double> &P;
@@ -112,7 +116,7 @@ struct GridHam {
         double s, c;
         trig(stage, th, s, c);
         double F[5], Fr[5], Ft[5];
-        grid_eval(A, r, th, F, Fr, Ft);
+        grid_eval<Node>(A, r, th, F, Fr, Ft);
         const double s2 = s * s;
         const double al = F[0], be = F[1];
         const double ia = recip(al);
@@ -151,6 +155,7 @@ __device__ __forceinline__ bool inside(const GridArgs &A, double r, double th)
 
 // Two waves per SIMD: left alone the compiler spills a few values to AGPRs past 256
 // registers, which leaves one wave per SIMD to hide the gathers' latency.
+template <typename Node>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8)))
 rk4_grid_kernel(GridArgs A)
 {
@@ -164,7 +169,7 @@ rk4_grid_kernel(GridArgs A)
     const HamConst<double> P{y[4], y[7], 0.0, 0.0};
     int32_t taken = 0;
     for (int32_t k = 0; k < A.n_steps && st == kActive; ++k) {
-        GridHam f{A, P, {0.0, 0.0, 1.0}};
+        GridHam<Node> f{A, P, {0.0, 0.0, 1.0}};
         double y1[8], sr[3];
         rk4_ham_step(f, A.h, y, y1, sr);
         ++taken;
@@ -193,8 +198,9 @@ rk4_grid_kernel(GridArgs A)
     A.steps[i] += taken;
 }
 
-// Kerr's 3+1 functions (Section 2) at every node.
-__global__ void __launch_bounds__(256) grid_fill_kerr_kernel(double *nodes, int32_t nr, int32_t nth,
+// Kerr's 3+1 functions (Section 2) at every node, computed in FP64 and stored as Node.
+template <typename Node>
+__global__ void __launch_bounds__(256) grid_fill_kerr_kernel(Node *nodes, int32_t nr, int32_t nth,
                                                              double r0, double dr, double th0,
                                                              double dth, double M, double a)
 {
@@ -208,22 +214,26 @@ __global__ void __launch_bounds__(256) grid_fill_kerr_kernel(double *nodes, int3
     const double rho2 = r * r + a * a * c * c;
     const double Delta = r * r - 2.0 * M * r + a * a;
     const double Sigma = r2a2 * r2a2 - a * a * Delta * s * s;
-    double *F = nodes + p * 5;
-    F[0] = sqrt(rho2 * Delta / Sigma);
-    F[1] = -2.0 * M * a * r / Sigma;
-    F[2] = rho2 / Delta;
-    F[3] = rho2;
-    F[4] = Sigma / rho2;
+    Node *F = nodes + p * 5;
+    F[0] = (Node)sqrt(rho2 * Delta / Sigma);
+    F[1] = (Node)(-2.0 * M * a * r / Sigma);
+    F[2] = (Node)(rho2 / Delta);
+    F[3] = (Node)rho2;
+    F[4] = (Node)(Sigma / rho2);
 }
 
 }  // namespace
 
-int launch_grid_fill_kerr(const malbec_grid &g, double M, double a, double *nodes, hipStream_t s)
+int launch_grid_fill_kerr(const malbec_grid &g, double M, double a, void *nodes, hipStream_t s)
 {
     const int block = 256;
     const int64_t np = (int64_t)g.nr * g.nth;
-    hipLaunchKernelGGL(grid_fill_kerr_kernel, dim3(grid_for(np, block)), dim3(block), 0, s, nodes,
-                       g.nr, g.nth, g.r0, g.dr, g.th0, g.dth, M, a);
+    if (g.node_precision == MALBEC_GRID_F32)
+        hipLaunchKernelGGL(grid_fill_kerr_kernel<float>, dim3(grid_for(np, block)), dim3(block), 0, s,
+                           (float *)nodes, g.nr, g.nth, g.r0, g.dr, g.th0, g.dth, M, a);
+    else
+        hipLaunchKernelGGL(grid_fill_kerr_kernel<double>, dim3(grid_for(np, block)), dim3(block), 0,
+                           s, (double *)nodes, g.nr, g.nth, g.r0, g.dr, g.th0, g.dth, M, a);
     MALBEC_LAUNCH_CHECK("grid_fill_kerr_kernel");
     return MALBEC_OK;
 }
@@ -256,7 +266,10 @@ int launch_integrate_grid(const malbec_run &run, const malbec_grid &g, int64_t n
     const int64_t chunk = run.steps_per_chunk > 0 ? run.steps_per_chunk : total;
     for (int64_t k0 = 0; k0 < total; k0 += chunk) {
         A.n_steps = (int32_t)((total - k0) < chunk ? (total - k0) : chunk);
-        hipLaunchKernelGGL(rk4_grid_kernel, dim3(grid_for(n, block)), dim3(block), 0, s, A);
+        if (g.node_precision == MALBEC_GRID_F32)
+            hipLaunchKernelGGL(rk4_grid_kernel<float>, dim3(grid_for(n, block)), dim3(block), 0, s, A);
+        else
+            hipLaunchKernelGGL(rk4_grid_kernel<double>, dim3(grid_for(n, block)), dim3(block), 0, s, A);
         MALBEC_LAUNCH_CHECK("rk4_grid_kernel");
     }
     return MALBEC_OK;

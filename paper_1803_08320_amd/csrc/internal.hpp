@@ -87,7 +87,7 @@ int launch_adaptive_order(const StTable &T, const int32_t *st_of_lane, int64_t n
                           const double *state, const double *tau, const int32_t *status,
                           double tau_end, uint32_t *order, uint32_t *keys, void *ws,
                           hipStream_t s);
-int launch_grid_fill_kerr(const malbec_grid &g, double M, double a, double *nodes, hipStream_t s);
+int launch_grid_fill_kerr(const malbec_grid &g, double M, double a, void *nodes, hipStream_t s);
 int launch_integrate_grid(const malbec_run &run, const malbec_grid &g, int64_t n, double *state,
                           int32_t *status, int32_t *steps, hipStream_t s);
 int launch_integrate_record(const malbec_run &run, const StTable &T, const int32_t *st_of_lane,

@@ -49,7 +49,7 @@ def test_struct_layout_matches_header(m, tmp_path):
                    "#define O(T, f) printf(#T \".\" #f \" %zu\\n\", offsetof(T, f));\n"
                    "int main(void){P(malbec_spacetime)P(malbec_batch)P(malbec_ic_spec)"
                    "P(malbec_run)P(malbec_camera)P(malbec_adaptive)O(malbec_adaptive, max_attempts)"
-                   "P(malbec_grid)O(malbec_grid, r_stop)O(malbec_grid, nodes)"
+                   "P(malbec_grid)O(malbec_grid, r_stop)O(malbec_grid, nodes)O(malbec_grid, node_precision)"
                    "O(malbec_adaptive, steps_per_chunk)O(malbec_adaptive, schedule)O(malbec_ic_spec, rows)O(malbec_ic_spec, max_attempts)"
                    "O(malbec_run, checkpoint_every)O(malbec_run, persistent)O(malbec_run, formulation)"
                    "O(malbec_camera, max_steps)O(malbec_camera, persistent)"
@@ -67,6 +67,7 @@ def test_struct_layout_matches_header(m, tmp_path):
     assert int(got["malbec_grid"]) == C.sizeof(m.c_grid)
     assert int(got["malbec_grid.r_stop"]) == m.c_grid.r_stop.offset
     assert int(got["malbec_grid.nodes"]) == m.c_grid.nodes.offset
+    assert int(got["malbec_grid.node_precision"]) == m.c_grid.node_precision.offset
     assert int(got["malbec_adaptive.max_attempts"]) == m.c_adaptive.max_attempts.offset
     assert int(got["malbec_adaptive.steps_per_chunk"]) == m.c_adaptive.steps_per_chunk.offset
     assert int(got["malbec_adaptive.schedule"]) == m.c_adaptive.schedule.offset
@@ -262,7 +263,8 @@ def test_adaptive_order_workspace_and_argument_errors(m):
     (dict(nr=3), {}, -1), (dict(dr=0.0), {}, -1), (dict(th0=0.0), {}, -1),
     (dict(dth=1.0), {}, -1), (dict(r_stop=1.0), {}, -1), (dict(nodes=None), {}, -1),
     ({}, dict(formulation=0), -1), ({}, dict(precision=1), -4), ({}, dict(persistent=1), -4),
-    ({}, dict(r_escape=100.0), -1), ({}, dict(h=-1.0), -1),
+    ({}, dict(r_escape=100.0), -1), ({}, dict(h=-1.0), -1), (dict(node_precision=2), {}, -1),
+    (dict(node_precision=-1), {}, -1),
 ])
 def test_grid_argument_errors(m, kw, run_kw, expect):
     d = dict(nr=16, nth=8, r0=2.5, dr=0.5, th0=0.5, dth=0.2, r_stop=3.2, nodes=0x1000)

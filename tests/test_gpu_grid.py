@@ -44,6 +44,27 @@ def gpu_grid_from(m, G, r_stop):
     return m.Grid(to_dev(G.nodes, torch.float64), G.r0, G.dr, G.th0, G.dth, r_stop)
 
 
+def f32_grids(orc, m, G, r_stop):
+    """The oracle's grid with its node values rounded to single precision (the values a
+    float-node grid stores): widened back to FP64 for the oracle, as float32 for the
+    device."""
+    import torch
+    n32 = G.nodes.astype(np.float32)
+    G32 = orc.Grid(n32.astype(np.float64), G.r0, G.dr, G.th0, G.dth)
+    return G32, m.Grid(to_dev(n32, torch.float32), G.r0, G.dr, G.th0, G.dth, r_stop)
+
+
+def assert_float_nodes(got, want64):
+    """Float node values from the device fill: the oracle's FP64 values rounded to
+    nearest, to within one unit in the float's last place (the device's and the
+    oracle's FP64 values may lie on either side of a rounding boundary)."""
+    assert got.dtype == np.float32
+    want = want64.astype(np.float32)
+    diff = np.abs(got.astype(np.float64) - want.astype(np.float64))
+    assert np.all(diff <= np.spacing(np.abs(want)).astype(np.float64))
+    assert (diff == 0).mean() > 0.999
+
+
 def run_gpu(m, grid, z0, h, n_steps, r_escape, **kw):
     import torch
     n = z0.shape[1]
@@ -61,6 +82,32 @@ def test_grid_fill_matches_oracle(m, orc):
                         r_stop=2.5)
         got = g.nodes.cpu().numpy()
         assert np.max(np.abs(got - G.nodes) / (np.abs(G.nodes) + 1.0)) < 1e-14
+
+
+def test_grid_fill_f32_matches_oracle(m, orc):
+    import torch
+    for a in (0.0, 0.9, 0.998):
+        G = orc.grid_kerr(1.0, a, GRID["nr"], GRID["nth"], 2.1, GRID["dr"], GRID["th0"], GRID["dth"])
+        g = m.grid_kerr(1.0, a, GRID["nr"], GRID["nth"], 2.1, GRID["dr"], GRID["th0"], GRID["dth"],
+                        r_stop=2.5, node_dtype=torch.float32)
+        assert_float_nodes(g.nodes.cpu().numpy(), G.nodes)
+
+
+@pytest.mark.parametrize("a,n", [(0.9, 600), (0.0, 300)])
+def test_grid_integration_parity_f32_nodes(m, orc, a, n):
+    """Float node values: the kernel widens them on load, the oracle integrates on the
+    same rounded values in FP64; several blocks and a ragged tail, 3,000 steps."""
+    st = [(1.0, a)]
+    r_stop = 1.2 * r_plus(a)
+    G = orc.grid_kerr(1.0, a, r0=1.05 * r_plus(a), **GRID)
+    G32, g32 = f32_grids(orc, m, G, r_stop)
+    rc, s0, _, _ = orc.ic_constants(95, st, n, KERR_RANGES)
+    z0 = lower(orc, st, s0)
+    got = run_gpu(m, g32, z0, 0.02, 3000, 55.0)
+    ref = orc.integrate_grid(G32, z0, 0.02, 3000, r_stop=r_stop, r_escape=55.0)
+    compare(orc, st, z0, *got, *ref,
+            lambda p0: orc.integrate_grid(G32, p0, 0.02, 3000, r_stop=r_stop, r_escape=55.0))
+    assert np.array_equal(got[0][4], z0[4]) and np.array_equal(got[0][7], z0[7])
 
 
 @pytest.mark.parametrize("a,n", [(0.9, 600), (0.0, 300)])
@@ -103,15 +150,17 @@ def test_off_grid_stops_and_chunking(m, orc):
         assert np.array_equal(x, y)
 
 
-def test_gridded_kerr_tracks_analytic_kerr(m, orc):
+@pytest.mark.parametrize("node_dtype", ["float64", "float32"])
+def test_gridded_kerr_tracks_analytic_kerr(m, orc, node_dtype):
     """The same orbits in the gridded and in the analytic metric (Hamiltonian form):
-    differences at the interpolation-error level."""
+    differences at the interpolation-error level, with node values stored in double
+    or in single precision."""
     import torch
     st = [(1.0, 0.9)]
     rc, s0, _, _ = orc.ic_constants(93, st, 256, ((6.0, 20.0),) + KERR_RANGES[1:])
     z0 = lower(orc, st, s0)
     g = m.grid_kerr(1.0, 0.9, 801, 401, 1.5, 60.0 / 800, 0.1, (math.pi - 0.2) / 400,
-                    1.2 * r_plus(0.9))
+                    1.2 * r_plus(0.9), node_dtype=getattr(torch, node_dtype))
     got = run_gpu(m, g, z0, 0.02, 2000, 55.0)
     x = to_dev(z0, torch.float64)
     status, steps = m.new_lane_arrays(256)
@@ -122,21 +171,28 @@ def test_gridded_kerr_tracks_analytic_kerr(m, orc):
     assert mixed_rel(got[0][:, both], ana[:, both]).max() < 1e-4
 
 
-def test_grid_full_size_sampled(m, orc):
-    """The benchmark's gridded launch: 1,048,576 Kerr a = 0.9 lanes x 2,000 steps on
+@pytest.mark.parametrize("node_dtype", ["float64", "float32"])
+def test_grid_full_size_sampled(m, orc, node_dtype):
+    """The benchmark's gridded launches: 1,048,576 Kerr a = 0.9 lanes x 2,000 steps on
     an 801 x 401 grid filled on the device (all nodes checked against the oracle's
-    fill); 256 strided lanes hold the oracle's initial data and are compared with the
-    oracle's integration on its own grid."""
+    fill), node values in double or in single precision; 256 strided lanes hold the
+    oracle's initial data and are compared with the oracle's integration on its own
+    grid (for float nodes: its values rounded to float, which the device grid then
+    holds too)."""
     import torch
     from parity import mixed_rel
     st = [(1.0, 0.9)]
     n = 1 << 20
     geo = (1.0, 0.9, 801, 401, 1.5, 60.0 / 800, 0.1, (math.pi - 0.2) / 400)
     r_stop = 1.2 * r_plus(0.9)
-    g = m.grid_kerr(*geo, r_stop)
+    g = m.grid_kerr(*geo, r_stop, node_dtype=getattr(torch, node_dtype))
     G = orc.grid_kerr(*geo)
     got_nodes = g.nodes.cpu().numpy()
-    assert np.max(np.abs(got_nodes - G.nodes) / (np.abs(G.nodes) + 1.0)) < 1e-14
+    if node_dtype == "float64":
+        assert np.max(np.abs(got_nodes - G.nodes) / (np.abs(G.nodes) + 1.0)) < 1e-14
+    else:
+        assert_float_nodes(got_nodes, G.nodes)
+        G, g = f32_grids(orc, m, G, r_stop)
     del got_nodes
     spec = m.ICSpec(mode=m.IC_CONSTANTS, seed=2, r_range=KERR_RANGES[0], th_range=KERR_RANGES[1],
                     E_range=KERR_RANGES[2], Lz_range=KERR_RANGES[3], Q_range=KERR_RANGES[4])
