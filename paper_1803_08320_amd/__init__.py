@@ -349,12 +349,14 @@ def integrate_adaptive(state: torch.Tensor, tau: torch.Tensor, h: torch.Tensor,
                        max_attempts: int = 1 << 20, horizon_factor: float = 1.01,
                        r_escape: float = 1500.0, block: int = 0, persistent: bool = True,
                        steps_per_chunk: int = 0, st_of_lane: Optional[torch.Tensor] = None,
-                       ws: Optional[torch.Tensor] = None, schedule: str = "index"):
+                       ws: Optional[torch.Tensor] = None, schedule: Optional[str] = None):
     """Dormand-Prince 5(4) with per-lane step size up to tau_end; state[8, n], tau and h
     (float64[n]), status, steps and rejects (int32[n]) in/out.  schedule: "index" or
     "periapsis" (persistent only: lanes handed out smallest periapsis first; the results
-    are the same)."""
+    are the same); None = "periapsis" for a persistent launch, else "index"."""
     n = state.shape[-1]
+    if schedule is None:
+        schedule = "periapsis" if persistent else "index"
     sched = {"index": SCHED_INDEX, "periapsis": SCHED_PERIAPSIS}[schedule]
     ad = c_adaptive(tau_end, rtol, atol, fac, facmin, facmax, max_attempts, horizon_factor,
                     r_escape, block, int(persistent), steps_per_chunk, sched)
