@@ -37,8 +37,8 @@ PEAK_FP64_VECTOR_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 128 FP64 flop/clk/CU
 # taken again.
 KERNEL_SOURCES = ("integrate.hip", "kerr_device.hpp", "kerr_accel.hpp", "ham_accel.hpp",
                   "persistent.hpp")
-TRAFFIC = {"sources_sha256": "98dd324c8df03a99c7a7651c9470a94bc1261a8620fdfc29fee5b6ff129dd7db",
-           "fetch_kib": 36951.5625, "fetch_scale": 1048576 / 524307.75,
+TRAFFIC = {"sources_sha256": "44d7fb634ab7e0e329bd0874ed3b0c49ac4a98b68ca0d597565fc3e5b327bd21",
+           "fetch_kib": 36951.0, "fetch_scale": 1048576 / 524308.25,
            "write_kib": 73728.0, "write_scale": 1048576 / 1048576.0}
 
 

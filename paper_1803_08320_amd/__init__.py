@@ -42,10 +42,10 @@ MAX_SPACETIMES = 64
 # Algorithmic FP64 flops of one RK4 step of one lane as implemented (static count of
 # csrc/kerr_accel.hpp and csrc/ham_accel.hpp by csrc/flopcount.cpp: add/sub/mul/div 1,
 # fma 2, sincos 2): Christoffel form, and Hamilton's equations.
-FLOPS_PER_STEP_F64 = 522
+FLOPS_PER_STEP_F64 = 514
 FLOPS_PER_STEP_F64_HAM = 336
 # one Dormand-Prince 5(4) attempt (six right-hand sides and the tableau; csrc/dp45.hpp)
-FLOPS_PER_ATTEMPT_DP45 = 1036
+FLOPS_PER_ATTEMPT_DP45 = 1024
 
 
 class MalbecError(RuntimeError):

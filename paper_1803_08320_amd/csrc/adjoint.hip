@@ -62,21 +62,19 @@ __device__ __forceinline__ void vjp_accel(double M, double a, double r, double t
     B.Dirho2 = b_ar * X.Fr;
     const double bFth = b_ath * K.irho2;
     B.irho2 = b_ath * X.Fth;
-    // Fr = Qr - dgrr_r urur + r uthuth + c1x2 uruth
-    // Fth = Qth - c1 urur + a2sc uthuth - twor uruth
-    const double urur = ur * ur, uthuth = uth * uth, uruth = ur * uth;
+    // Fr = Qr - dgrr_r urur + r uthuth + c1 uruth2
+    // Fth = Qth - c1 urur + a2sc uthuth - r uruth2,   uruth2 = 2 ur uth
+    const double urur = ur * ur, uthuth = uth * uth, uruth2 = (ur + ur) * uth;
     const double bQr = bFr, bQth = bFth;
     B.dgrr_r = -bFr * urur;
-    B.c1 = -bFth * urur;
-    B.c1x2 = bFr * uruth;
-    B.r = bFr * uthuth;
-    B.twor = -bFth * uruth;
+    B.c1 = fma(bFr, uruth2, -bFth * urur);
+    B.r = fma(bFr, uthuth, -bFth * uruth2);
     B.a2sc = bFth * uthuth;
     const double burur = -fma(bFr, K.dgrr_r, bFth * K.c1);
     const double buthuth = fma(bFr, K.r, bFth * K.a2sc);
-    const double buruth = fma(bFr, K.c1x2, -bFth * K.twor);
-    double bur = fma(2.0 * ur, burur, uth * buruth);
-    double buth = fma(2.0 * uth, buthuth, ur * buruth);
+    const double buruth2 = fma(bFr, K.c1, -bFth * K.r);
+    double bur = 2.0 * fma(ur, burur, uth * buruth2);
+    double buth = 2.0 * fma(uth, buthuth, ur * buruth2);
     // Qr = ut Pt_r + uph Pp_r, Qth = ut Pt_th + uph Pp_th
     double but = fma(bQr, X.Pt_r, bQth * X.Pt_th);
     double buph = fma(bQr, X.Pp_r, bQth * X.Pp_th);
@@ -108,10 +106,9 @@ __device__ __forceinline__ void vjp_accel(double M, double a, double r, double t
     kerr_coef<D>(D(M), D(a), D(r, 1.0, 0.0), D(s, 0.0, c), D(c, 0.0, -s), Kd);
     double sr = 0.0, st = 0.0;
 #define MALBEC_C(f) sr = fma(B.f, Kd.f.dr, sr); st = fma(B.f, Kd.f.dth, st);
-    MALBEC_C(r) MALBEC_C(twor) MALBEC_C(Rtt) MALBEC_C(Rtp) MALBEC_C(Rpp) MALBEC_C(irho2)
+    MALBEC_C(r) MALBEC_C(Rtt) MALBEC_C(Rtp) MALBEC_C(Rpp) MALBEC_C(irho2)
     MALBEC_C(Dirho2) MALBEC_C(a2sc) MALBEC_C(dgtt_r) MALBEC_C(dgtt_th) MALBEC_C(dgtp_r)
     MALBEC_C(dgtp_th) MALBEC_C(dgpp_r) MALBEC_C(dgpp_th) MALBEC_C(dgrr_r) MALBEC_C(c1)
-    MALBEC_C(c1x2)
 #undef MALBEC_C
     rbar = sr;
     thbar = st;

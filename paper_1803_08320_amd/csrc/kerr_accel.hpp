@@ -57,11 +57,11 @@ MALBEC_HD inline float recip(float x)
 // factor 2: Rtt = 2 g_pp / (Delta s^2), Rtp = 2 g_tp / (Delta s^2),
 // Rpp = 2 g_tt / (Delta s^2), the inverse block being
 // -(1/2) [[Rtt, -Rtp], [-Rtp, Rpp]].  Also 1/rho^2, Delta/rho^2, and
-// c1 = a^2 s c / Delta = -(1/2) d_theta g_rr, c1x2 = 2 c1.
+// c1 = a^2 s c / Delta = -(1/2) d_theta g_rr.
 template <typename T>
 struct KerrCoef {
-    T r, twor, Rtt, Rtp, Rpp, irho2, Dirho2, a2sc;
-    T dgtt_r, dgtt_th, dgtp_r, dgtp_th, dgpp_r, dgpp_th, dgrr_r, c1, c1x2;
+    T r, Rtt, Rtp, Rpp, irho2, Dirho2, a2sc;
+    T dgtt_r, dgtt_th, dgtp_r, dgtp_th, dgpp_r, dgpp_th, dgrr_r, c1;
 };
 
 template <typename T>
@@ -73,21 +73,22 @@ MALBEC_HD inline void kerr_coef(T M, T a, T r, T s, T c, KerrCoef<T> &K)
     const T r2 = r * r;
     const T A = r2 + a2;                    // r^2 + a^2
     const T rho2 = fma(a2, c * c, r2);      // r^2 + a^2 cos^2
-    const T Delta = fma(-(M + M), r, A);    // r^2 - 2 M r + a^2
+    const T M2 = M + M;
+    const T Delta = fma(-M2, r, A);         // r^2 - 2 M r + a^2
     const T Ds2 = Delta * s2;
     const T inv = recip(rho2 * Ds2);        // 1 / (rho^2 Delta s^2)
     const T iDs2 = inv * rho2;              // 1 / (Delta s^2)
     const T irho2 = inv * Ds2;              // 1 / rho^2
     const T iDelta = iDs2 * s2;             // 1 / Delta
-    const T twor = r + r;
-
     const T mi = M * irho2;
-    const T q = mi * twor;                  // 2 M r / rho^2;  g_tt = q - 1
+    const T ri = r * irho2;                 // r / rho^2
+    const T q = M2 * ri;                    // 2 M r / rho^2;  g_tt = q - 1
     const T qs2 = q * s2;                   // g_tp = -a q s^2
     const T gpp_os2 = fma(a2, qs2, A);      // g_pp = (r^2 + a^2 + a^2 q s^2) s^2
 
-    // half partial derivatives of q and of q s^2
-    const T hdq_r = mi * fma(T(-2), r2 * irho2, T(1));
+    // half partial derivatives of q and of q s^2:
+    // (1/2) d_r q = M (rho^2 - 2 r^2) / rho^4 = mi - q r / rho^2
+    const T hdq_r = fma(-q, ri, mi);
     const T a2sc = a2 * sc;
     const T hdq_th = (q * irho2) * a2sc;
     const T hdqs2_th = fma(hdq_th, s2, q * sc);
@@ -95,7 +96,6 @@ MALBEC_HD inline void kerr_coef(T M, T a, T r, T s, T c, KerrCoef<T> &K)
     const T iDelta2 = iDelta + iDelta;
 
     K.r = r;
-    K.twor = twor;
     K.Rtt = iDelta2 * gpp_os2;
     K.Rtp = (-a * q) * iDelta2;
     K.Rpp = iDs2 * fma(T(2), q, T(-2));
@@ -110,7 +110,6 @@ MALBEC_HD inline void kerr_coef(T M, T a, T r, T s, T c, KerrCoef<T> &K)
     K.dgpp_th = fma(-a * K.dgtp_th, s2, gpp_os2 * sc);    // a^2 hd(q s^2) s^2 + g_pp/s^2 sc
     K.dgrr_r = iDelta * fma(-grr, r - M, r);              // (r - g_rr (r - M)) / Delta
     K.c1 = a2sc * iDelta;
-    K.c1x2 = K.c1 + K.c1;
 }
 
 // Intermediate products of the contraction (kept for the adjoint).
@@ -135,11 +134,11 @@ MALBEC_HD inline void kerr_contract(const KerrCoef<T> &K, T ut, T ur, T uth, T u
     const T Wp = fma(ur, Pp_r, uth * Pp_th);
     const T Qr = fma(ut, Pt_r, uph * Pp_r);    // (1/2) (t,phi) part of (d_r g_ab) u^a u^b
     const T Qth = fma(ut, Pt_th, uph * Pp_th); // (1/2) (t,phi) part of (d_th g_ab) u^a u^b
-    const T urur = ur * ur, uthuth = uth * uth, uruth = ur * uth;
+    const T urur = ur * ur, uthuth = uth * uth, uruth2 = (ur + ur) * uth;  // 2 ur uth
     // F_r = Qr - (1/2) d_r g_rr ur^2 + r uth^2 - d_th g_rr ur uth
-    const T Fr = fma(K.c1x2, uruth, fma(K.r, uthuth, fma(-K.dgrr_r, urur, Qr)));
+    const T Fr = fma(K.c1, uruth2, fma(K.r, uthuth, fma(-K.dgrr_r, urur, Qr)));
     // F_th = Qth + (1/2) d_th g_rr ur^2 + a^2 s c uth^2 - 2 r ur uth
-    const T Fth = fma(-K.twor, uruth, fma(K.a2sc, uthuth, fma(-K.c1, urur, Qth)));
+    const T Fth = fma(-K.r, uruth2, fma(K.a2sc, uthuth, fma(-K.c1, urur, Qth)));
 
     // raise with the (t, phi) block inverse and g^rr, g^thth
     at = fma(K.Rtt, Wt, -K.Rtp * Wp);
