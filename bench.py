@@ -37,8 +37,8 @@ PEAK_FP64_VECTOR_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 128 FP64 flop/clk/CU
 # taken again.
 KERNEL_SOURCES = ("integrate.hip", "kerr_device.hpp", "kerr_accel.hpp", "ham_accel.hpp",
                   "persistent.hpp")
-TRAFFIC = {"sources_sha256": "44d7fb634ab7e0e329bd0874ed3b0c49ac4a98b68ca0d597565fc3e5b327bd21",
-           "fetch_kib": 36951.0, "fetch_scale": 1048576 / 524308.25,
+TRAFFIC = {"sources_sha256": "5f323df78a76efa963e1b0720e5805501f65042702c1be4d93181fad69623536",
+           "fetch_kib": 36950.9375, "fetch_scale": 1048576 / 524308.0625,
            "write_kib": 73728.0, "write_scale": 1048576 / 1048576.0}
 
 

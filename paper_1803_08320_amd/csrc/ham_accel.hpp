@@ -65,7 +65,8 @@ MALBEC_HD inline void kerr_ham(T M, T a, T r, T s, T c, T pr, T pth, const HamCo
     dt = fma(a * s, w, -A * PD) * irho2;
     dph = fma(w, is, -a * PD) * irho2;
     const T rM = r - M;
-    const T hdrN = fma(rM, prpr, -PD * fma(-PD, rM, (r + r) * P.pt));
+    // 2 r p_t as r (2 p_t): the same exact doubling, with 2 p_t constant along the lane
+    const T hdrN = fma(rM, prpr, -PD * fma(-PD, rM, r * (P.pt + P.pt)));
     dpr = fma(r, twoH, -hdrN) * irho2;
     const T hdthN = (w * c) * fma(-P.pph, is * is, P.apt);
     dpth = -fma(a2 * (s * c), twoH, hdthN) * irho2;
