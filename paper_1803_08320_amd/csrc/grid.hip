@@ -17,6 +17,8 @@
 // 640 B of grid data (320 B as floats), read from the caches (the grid is small next
 // to L2 + MALL); those gathers, not the work per lane-step (~4 x (interpolation
 // 220 fma + metric algebra)), set the rate.
+#include <type_traits>
+
 #include "internal.hpp"
 
 namespace malbec {
@@ -61,6 +63,47 @@ __device__ __forceinline__ int32_t cell(double x, double x0, double ih, int32_t 
     return (int32_t)f;
 }
 
+// Stencil cache of one lane for float node values: the 16 nodes x 5 floats of the
+// lane's current cell in LDS, as 20 16-byte chunks with the block's lanes interleaved
+// (chunk m of thread t at lds[m * kCacheLanes + t]: conflict-free 16-byte reads), and
+// the cell it holds.  The four stage points of a step, and the next steps, mostly lie
+// in the same cell (a stage moves a few thousandths in r and theta against cells of
+// 0.075 and 0.0075 on the benchmark grid), so most evaluations read LDS instead of
+// gathering four rows through the L1.  320 B per lane: two blocks of 256 fill a CU's
+// 160 KB, the occupancy the kernel's registers allow anyway.
+constexpr int kCacheLanes = 256;
+struct StencilCache {
+    float4 *lds;     // &cache[threadIdx.x]
+    int32_t ci, cj;  // cell held (-1: none)
+};
+
+// Lagrange contraction of one stencil row (4 nodes x 5 values, element b * 5 + k,
+// widened to FP64 where used).
+template <typename V>
+__device__ __forceinline__ void contract_row(const V *f, double wra, double dwra,
+                                             const double wt[4], const double dwt[4], double F[5],
+                                             double Fr[5], double Ft[5])
+{
+    double v[5], vt[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) { v[k] = 0.0; vt[k] = 0.0; }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            const double x = (double)f[b * 5 + k];
+            v[k] = fma(wt[b], x, v[k]);
+            vt[k] = fma(dwt[b], x, vt[k]);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        F[k] = fma(wra, v[k], F[k]);
+        Fr[k] = fma(dwra, v[k], Fr[k]);
+        Ft[k] = fma(wra, vt[k], Ft[k]);
+    }
+}
+
 // F, dF/dr, dF/dtheta of the five functions at (r, theta).
 template <typename Node>
 __device__ __forceinline__ void grid_eval(const GridArgs &A, double r, double th, double F[5],
@@ -100,11 +143,61 @@ __device__ __forceinline__ void grid_eval(const GridArgs &A, double r, double th
     for (int k = 0; k < 5; ++k) { Fr[k] *= A.idr; Ft[k] *= A.idth; }
 }
 
+__device__ __forceinline__ StencilCache *cache_arg(StencilCache &C) { return &C; }
+__device__ __forceinline__ int cache_arg(int) { return 0; }
+
+// The same for float node values, through the lane's stencil cache (C), refilled
+// when the cell changes.
+__device__ __forceinline__ void grid_eval_cached(const GridArgs &A, double r, double th, double F[5],
+                                                 double Fr[5], double Ft[5], StencilCache *C)
+{
+    double ur, ut, wr[4], dwr[4], wt[4], dwt[4];
+    const int32_t i = cell(r, A.r0, A.idr, A.nr, ur);
+    const int32_t j = cell(th, A.th0, A.idth, A.nth, ut);
+    lagrange4(ur, wr, dwr);
+    lagrange4(ut, wt, dwt);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) { F[k] = 0.0; Fr[k] = 0.0; Ft[k] = 0.0; }
+    if (i != C->ci || j != C->cj) {
+        // refill: the four rows (80 contiguous bytes each) into the lane's chunks
+#pragma unroll 1
+        for (int a = 0; a < 4; ++a) {
+            const float *row = (const float *)A.nodes + ((int64_t)(i - 1 + a) * A.nth + (j - 1)) * 5;
+            float g[20];
+#pragma unroll
+            for (int e = 0; e < 20; ++e) g[e] = row[e];
+#pragma unroll
+            for (int m = 0; m < 5; ++m)
+                C->lds[(a * 5 + m) * kCacheLanes] =
+                    make_float4(g[4 * m], g[4 * m + 1], g[4 * m + 2], g[4 * m + 3]);
+        }
+        C->ci = i;
+        C->cj = j;
+    }
+#pragma unroll 1
+    for (int a = 0; a < 4; ++a) {
+        float f[20];
+#pragma unroll
+        for (int m = 0; m < 5; ++m) {
+            const float4 q = C->lds[(a * 5 + m) * kCacheLanes];
+            f[4 * m] = q.x;
+            f[4 * m + 1] = q.y;
+            f[4 * m + 2] = q.z;
+            f[4 * m + 3] = q.w;
+        }
+        contract_row(f, wr[a], dwr[a], wt, dwt, F, Fr, Ft);
+    }
+#pragma unroll
+    for (int k = 0; k < 5; ++k) { Fr[k] *= A.idr; Ft[k] *= A.idth; }
+}
+
 // Canonical right-hand side with the gridded metric; records the stage point.
 template <typename Node>
 struct GridHam {
     const GridArgs &A;
     const HamConst<double> &P;
+    // the lane's stencil cache (float node values only)
+    std::conditional_t<std::is_same<Node, float>::value, StencilCache *, int> C;
     StageTrig trig;
     double st_r[4], st_th[4];
     __device__ __forceinline__ void operator()(int stage, double r, double th, double pr, double pth,
@@ -116,7 +209,10 @@ struct GridHam {
         double s, c;
         trig(stage, th, s, c);
         double F[5], Fr[5], Ft[5];
-        grid_eval<Node>(A, r, th, F, Fr, Ft);
+        if constexpr (std::is_same<Node, float>::value)
+            grid_eval_cached(A, r, th, F, Fr, Ft, C);
+        else
+            grid_eval<Node>(A, r, th, F, Fr, Ft);
         const double s2 = s * s;
         const double al = F[0], be = F[1];
         const double ia = recip(al);
@@ -167,9 +263,14 @@ rk4_grid_kernel(GridArgs A)
 #pragma unroll
     for (int k = 0; k < 8; ++k) y[k] = A.state[k * A.n + i];
     const HamConst<double> P{y[4], y[7], 0.0, 0.0};
+    std::conditional_t<std::is_same<Node, float>::value, StencilCache, int> C{};
+    if constexpr (std::is_same<Node, float>::value) {
+        __shared__ float4 cache[20 * kCacheLanes];
+        C = StencilCache{&cache[threadIdx.x], -1, -1};
+    }
     int32_t taken = 0;
     for (int32_t k = 0; k < A.n_steps && st == kActive; ++k) {
-        GridHam<Node> f{A, P, {0.0, 0.0, 1.0}};
+        GridHam<Node> f{A, P, cache_arg(C), {0.0, 0.0, 1.0}};
         double y1[8], sr[3];
         rk4_ham_step(f, A.h, y, y1, sr);
         ++taken;
