@@ -517,8 +517,10 @@ def main():
             "rk4_steps": n_g, "kernel_ms": 1e3 * dt,
             "vs_analytic_hamiltonian": (ls / dt) / result["hamiltonian"]["value"]
             if "hamiltonian" in result else None,
-            "gathered_bytes_per_lane_step": 4 * 16 * 40,
-            "gather_GB_per_s": 4 * 16 * 40 * ls / dt / 1e9,
+            # stencil bytes the interpolation reads per lane-step (mostly from the
+            # lanes' LDS stencil caches; the grid's rows only when a lane changes cell)
+            "stencil_bytes_per_lane_step": 4 * 16 * 40,
+            "stencil_GB_per_s": 4 * 16 * 40 * ls / dt / 1e9,
             "active_frac": float((status == 0).float().mean().item())}
         # the same grid with its node values stored in single precision (half the
         # gathered bytes; arithmetic in FP64), and how far its orbits end from the
@@ -537,8 +539,8 @@ def main():
         result["grid_3p1"]["node_f32"] = {
             "value": ls32 / dt32, "unit": "lane-steps/s", "kernel_ms": 1e3 * dt32,
             "speedup_vs_f64_nodes": (ls32 / dt32) / (ls / dt),
-            "gathered_bytes_per_lane_step": 4 * 16 * 20,
-            "gather_GB_per_s": 4 * 16 * 20 * ls32 / dt32 / 1e9,
+            "stencil_bytes_per_lane_step": 4 * 16 * 20,
+            "stencil_GB_per_s": 4 * 16 * 20 * ls32 / dt32 / 1e9,
             "pos_diff_vs_f64_nodes_p50": float(np.quantile(dpos, 0.5)),
             "pos_diff_vs_f64_nodes_p99": float(np.quantile(dpos, 0.99)),
             "status_agree_frac": float((status == st64).float().mean().item())}

@@ -13,10 +13,11 @@
 //   g^tt = -1/alpha^2, g^tphi = beta^phi/alpha^2,
 //   g^phph = 1/gamma_phph - (beta^phi)^2/alpha^2, g^rr = 1/gamma_rr, g^thth = 1/gamma_thth
 // and its r, theta derivatives, and Hamilton's equations (eq. Ham) on (x^mu, p_mu)
-// with classic RK4 (p_t and p_phi are constants).  Each right-hand side gathers
-// 640 B of grid data (320 B as floats), read from the caches (the grid is small next
-// to L2 + MALL); those gathers, not the work per lane-step (~4 x (interpolation
-// 220 fma + metric algebra)), set the rate.
+// with classic RK4 (p_t and p_phi are constants).  A right-hand side needs 640 B of
+// grid data (320 B as floats); each lane keeps its current cell's stencil in LDS
+// (StencilCache), so the rows are gathered from the caches only when a lane moves to
+// another cell, and the work per lane-step is ~4 x (interpolation 220 fma + metric
+// algebra).
 #include <type_traits>
 
 #include "internal.hpp"
@@ -63,17 +64,21 @@ __device__ __forceinline__ int32_t cell(double x, double x0, double ih, int32_t 
     return (int32_t)f;
 }
 
-// Stencil cache of one lane for float node values: the 16 nodes x 5 floats of the
-// lane's current cell in LDS, as 20 16-byte chunks with the block's lanes interleaved
+// Stencil cache of one lane: the 16 nodes x 5 values of the lane's current cell in
+// LDS, as 16-byte chunks (4 floats or 2 doubles) with the block's lanes interleaved
 // (chunk m of thread t at lds[m * kCacheLanes + t]: conflict-free 16-byte reads), and
 // the cell it holds.  The four stage points of a step, and the next steps, mostly lie
 // in the same cell (a stage moves a few thousandths in r and theta against cells of
 // 0.075 and 0.0075 on the benchmark grid), so most evaluations read LDS instead of
-// gathering four rows through the L1.  320 B per lane: two blocks of 256 fill a CU's
-// 160 KB, the occupancy the kernel's registers allow anyway.
+// gathering four rows through the L1.  320 B per lane with float nodes (two blocks of
+// 256 fill a CU's 160 KB: two waves per SIMD, as the registers allow) and 640 B with
+// double nodes (one block per CU, one wave per SIMD; the LDS reads need little
+// latency hiding).
 constexpr int kCacheLanes = 256;
+template <typename Node>
 struct StencilCache {
-    float4 *lds;     // &cache[threadIdx.x]
+    typedef typename std::conditional<std::is_same<Node, float>::value, float4, double2>::type Chunk;
+    Chunk *lds;      // &cache[threadIdx.x]
     int32_t ci, cj;  // cell held (-1: none)
 };
 
@@ -104,53 +109,17 @@ __device__ __forceinline__ void contract_row(const V *f, double wra, double dwra
     }
 }
 
-// F, dF/dr, dF/dtheta of the five functions at (r, theta).
-template <typename Node>
-__device__ __forceinline__ void grid_eval(const GridArgs &A, double r, double th, double F[5],
-                                          double Fr[5], double Ft[5])
-{
-    double ur, ut, wr[4], dwr[4], wt[4], dwt[4];
-    const int32_t i = cell(r, A.r0, A.idr, A.nr, ur);
-    const int32_t j = cell(th, A.th0, A.idth, A.nth, ut);
-    lagrange4(ur, wr, dwr);
-    lagrange4(ut, wt, dwt);
-#pragma unroll
-    for (int k = 0; k < 5; ++k) { F[k] = 0.0; Fr[k] = 0.0; Ft[k] = 0.0; }
-    // one stencil row (4 nodes, 160 or 80 contiguous bytes) in flight at a time
-#pragma unroll 1
-    for (int a = 0; a < 4; ++a) {
-        const Node *row = (const Node *)A.nodes + ((int64_t)(i - 1 + a) * A.nth + (j - 1)) * 5;
-        double v[5], vt[5];
-#pragma unroll
-        for (int k = 0; k < 5; ++k) { v[k] = 0.0; vt[k] = 0.0; }
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-#pragma unroll
-            for (int k = 0; k < 5; ++k) {
-                const double f = (double)row[b * 5 + k];
-                v[k] = fma(wt[b], f, v[k]);
-                vt[k] = fma(dwt[b], f, vt[k]);
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < 5; ++k) {
-            F[k] = fma(wr[a], v[k], F[k]);
-            Fr[k] = fma(dwr[a], v[k], Fr[k]);
-            Ft[k] = fma(wr[a], vt[k], Ft[k]);
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < 5; ++k) { Fr[k] *= A.idr; Ft[k] *= A.idth; }
-}
-
-__device__ __forceinline__ StencilCache *cache_arg(StencilCache &C) { return &C; }
-__device__ __forceinline__ int cache_arg(int) { return 0; }
-
 // The same for float node values, through the lane's stencil cache (C), refilled
 // when the cell changes.
-__device__ __forceinline__ void grid_eval_cached(const GridArgs &A, double r, double th, double F[5],
-                                                 double Fr[5], double Ft[5], StencilCache *C)
+// F, dF/dr, dF/dtheta of the five functions at (r, theta), through the lane's stencil
+// cache C (refilled from the grid when the cell changes).
+template <typename Node>
+__device__ __forceinline__ void grid_eval(const GridArgs &A, double r, double th, double F[5],
+                                          double Fr[5], double Ft[5], StencilCache<Node> *C)
 {
+    typedef typename StencilCache<Node>::Chunk Chunk;
+    constexpr int PER = 16 / sizeof(Node);   // values per chunk
+    constexpr int CH = 20 / PER;             // chunks per row
     double ur, ut, wr[4], dwr[4], wt[4], dwt[4];
     const int32_t i = cell(r, A.r0, A.idr, A.nr, ur);
     const int32_t j = cell(th, A.th0, A.idth, A.nth, ut);
@@ -159,31 +128,33 @@ __device__ __forceinline__ void grid_eval_cached(const GridArgs &A, double r, do
 #pragma unroll
     for (int k = 0; k < 5; ++k) { F[k] = 0.0; Fr[k] = 0.0; Ft[k] = 0.0; }
     if (i != C->ci || j != C->cj) {
-        // refill: the four rows (80 contiguous bytes each) into the lane's chunks
 #pragma unroll 1
         for (int a = 0; a < 4; ++a) {
-            const float *row = (const float *)A.nodes + ((int64_t)(i - 1 + a) * A.nth + (j - 1)) * 5;
-            float g[20];
+            const Node *row = (const Node *)A.nodes + ((int64_t)(i - 1 + a) * A.nth + (j - 1)) * 5;
+            Node g[20];
 #pragma unroll
             for (int e = 0; e < 20; ++e) g[e] = row[e];
 #pragma unroll
-            for (int m = 0; m < 5; ++m)
-                C->lds[(a * 5 + m) * kCacheLanes] =
-                    make_float4(g[4 * m], g[4 * m + 1], g[4 * m + 2], g[4 * m + 3]);
+            for (int m = 0; m < CH; ++m) {
+                Chunk q;
+                Node *qp = (Node *)&q;
+#pragma unroll
+                for (int e = 0; e < PER; ++e) qp[e] = g[PER * m + e];
+                C->lds[(a * CH + m) * kCacheLanes] = q;
+            }
         }
         C->ci = i;
         C->cj = j;
     }
 #pragma unroll 1
     for (int a = 0; a < 4; ++a) {
-        float f[20];
+        Node f[20];
 #pragma unroll
-        for (int m = 0; m < 5; ++m) {
-            const float4 q = C->lds[(a * 5 + m) * kCacheLanes];
-            f[4 * m] = q.x;
-            f[4 * m + 1] = q.y;
-            f[4 * m + 2] = q.z;
-            f[4 * m + 3] = q.w;
+        for (int m = 0; m < CH; ++m) {
+            const Chunk q = C->lds[(a * CH + m) * kCacheLanes];
+            const Node *qp = (const Node *)&q;
+#pragma unroll
+            for (int e = 0; e < PER; ++e) f[PER * m + e] = qp[e];
         }
         contract_row(f, wr[a], dwr[a], wt, dwt, F, Fr, Ft);
     }
@@ -197,7 +168,7 @@ struct GridHam {
     const GridArgs &A;
     const HamConst<double> &P;
     // the lane's stencil cache (float node values only)
-    std::conditional_t<std::is_same<Node, float>::value, StencilCache *, int> C;
+    StencilCache<Node> *C;  // the lane's stencil cache
     StageTrig trig;
     double st_r[4], st_th[4];
     __device__ __forceinline__ void operator()(int stage, double r, double th, double pr, double pth,
@@ -209,10 +180,7 @@ struct GridHam {
         double s, c;
         trig(stage, th, s, c);
         double F[5], Fr[5], Ft[5];
-        if constexpr (std::is_same<Node, float>::value)
-            grid_eval_cached(A, r, th, F, Fr, Ft, C);
-        else
-            grid_eval<Node>(A, r, th, F, Fr, Ft);
+        grid_eval<Node>(A, r, th, F, Fr, Ft, C);
         const double s2 = s * s;
         const double al = F[0], be = F[1];
         const double ia = recip(al);
@@ -249,8 +217,9 @@ __device__ __forceinline__ bool inside(const GridArgs &A, double r, double th)
     return r >= A.rlo && r <= A.rhi && th >= A.tlo && th <= A.thi;
 }
 
-// Two waves per SIMD: left alone the compiler spills a few values to AGPRs past 256
-// registers, which leaves one wave per SIMD to hide the gathers' latency.
+// At most 256 registers (the two waves per SIMD that the float-node cache's LDS
+// allows): left alone the compiler spills a few values to AGPRs past 256 registers.
+// The double-node cache takes a CU's whole LDS, so that kernel runs one wave per SIMD.
 template <typename Node>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8)))
 rk4_grid_kernel(GridArgs A)
@@ -263,14 +232,12 @@ rk4_grid_kernel(GridArgs A)
 #pragma unroll
     for (int k = 0; k < 8; ++k) y[k] = A.state[k * A.n + i];
     const HamConst<double> P{y[4], y[7], 0.0, 0.0};
-    std::conditional_t<std::is_same<Node, float>::value, StencilCache, int> C{};
-    if constexpr (std::is_same<Node, float>::value) {
-        __shared__ float4 cache[20 * kCacheLanes];
-        C = StencilCache{&cache[threadIdx.x], -1, -1};
-    }
+    typedef typename StencilCache<Node>::Chunk Chunk;
+    __shared__ Chunk cache[4 * (20 * sizeof(Node) / 16) * kCacheLanes];
+    StencilCache<Node> C{&cache[threadIdx.x], -1, -1};
     int32_t taken = 0;
     for (int32_t k = 0; k < A.n_steps && st == kActive; ++k) {
-        GridHam<Node> f{A, P, cache_arg(C), {0.0, 0.0, 1.0}};
+        GridHam<Node> f{A, P, &C, {0.0, 0.0, 1.0}};
         double y1[8], sr[3];
         rk4_ham_step(f, A.h, y, y1, sr);
         ++taken;
