@@ -211,3 +211,22 @@ def test_grid_full_size_sampled(m, orc, node_dtype):
     compare(orc, st, z0, *got, *ref,
             lambda p0: orc.integrate_grid(G, p0, 0.02, 2000, r_stop=r_stop, r_escape=55.0))
     assert (status == 0).float().mean().item() > 0.99
+
+
+@pytest.mark.parametrize("node_dtype", ["float64", "float32"])
+def test_stencil_cache_block_sizes_and_chunks_same_bits(m, orc, node_dtype):
+    """Each lane's LDS stencil cache is indexed by its thread in the block and starts
+    empty in every launch: blocks of 64, 128 and 256 lanes and launch-chunked runs give
+    the same bits (a ragged batch of 1,000 lanes that cross many cells in 3,000 steps)."""
+    import torch
+    st = [(1.0, 0.9)]
+    rc, s0, _, _ = orc.ic_constants(96, st, 1000, KERR_RANGES)
+    z0 = lower(orc, st, s0)
+    g = m.grid_kerr(1.0, 0.9, 401, 201, 1.5, 60.0 / 400, 0.1, (math.pi - 0.2) / 200,
+                    1.2 * r_plus(0.9), node_dtype=getattr(torch, node_dtype))
+    ref = run_gpu(m, g, z0, 0.02, 3000, 55.0)
+    assert (ref[1] == 0).mean() > 0.9
+    for kw in (dict(block=64), dict(block=128), dict(steps_per_chunk=701)):
+        got = run_gpu(m, g, z0, 0.02, 3000, 55.0, **kw)
+        for x, y in zip(ref, got):
+            assert np.array_equal(x, y), kw
