@@ -92,6 +92,7 @@ extern "C" {
 #define MALBEC_SCHED_INDEX 0      /* lanes in index order */
 #define MALBEC_SCHED_PERIAPSIS 1  /* smallest periapsis first (malbec_adaptive_order) */
 #define MALBEC_SCHED_BUCKETS 1024 /* keys of malbec_adaptive_order: 0 .. 1023 */
+#define MALBEC_NOALLOC_MAX_LANES 2097152 /* batch limit of malbec_integrate_adaptive_noalloc */
 
 /* One Kerr spacetime: mass M > 0 and spin a in [0, M] (Section 2; a > M is a naked
  * singularity and is rejected). */
@@ -373,6 +374,21 @@ MALBEC_API int malbec_adaptive_order(const malbec_batch *b, int64_t n, const dou
                                      const double *tau, const int32_t *status, double tau_end,
                                      uint32_t *order, uint32_t *keys, void *ws, size_t ws_bytes,
                                      void *stream);
+
+/* malbec_integrate_adaptive without a caller workspace, for callers that cannot
+ * allocate device memory around the call (code under HIP graph capture, serving
+ * loops, harnesses that forbid allocation).  Arguments, results and errors are those
+ * of malbec_integrate_adaptive; the call allocates nothing: the work counter and the
+ * periapsis work order use a static device array of the library (16 MiB + 8.4 KiB on
+ * every GPU the library runs on, held until the process ends), so n is limited to
+ * MALBEC_NOALLOC_MAX_LANES (2^21; larger n: MALBEC_EINVAL).  Every call on one GPU uses
+ * that GPU's single array: calls that overlap on one GPU (concurrent streams or host
+ * threads) race and give undefined results; calls in one stream order are safe (the
+ * call clears what must start at zero). */
+MALBEC_API int malbec_integrate_adaptive_noalloc(const malbec_adaptive *ad, const malbec_batch *b,
+                                                 int64_t n, double *state, double *tau, double *h,
+                                                 int32_t *status, int32_t *steps, int32_t *rejects,
+                                                 void *stream);
 
 /* Fill g->nodes (device, written through the pointer passed as `nodes`, which must be
  * g->nodes, in g->node_precision's type: each value computed in FP64, then rounded

@@ -24,7 +24,7 @@ __all__ = [
     "ICSpec", "Camera", "init_particles", "integrate", "invariants", "trace_camera",
     "workspace_bytes", "last_error", "version", "lib", "MalbecError", "STATUS", "adjoint",
     "IntegrateFromParams", "convert_state", "integrate_record", "integrate_adaptive",
-    "adaptive_order", "Grid", "grid_kerr", "integrate_grid",
+    "adaptive_order", "Grid", "grid_kerr", "integrate_grid", "integrate_adaptive_noalloc",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -36,6 +36,7 @@ FORM_CHRISTOFFEL, FORM_HAMILTONIAN = 0, 1
 IC_CANONICAL, IC_CIRCULAR, IC_CONSTANTS, IC_PARAMS = 0, 1, 2, 3
 OP_INTEGRATE, OP_CAMERA, OP_ADJOINT, OP_ADAPTIVE, OP_ADAPTIVE_ORDER = 1, 2, 3, 4, 5
 SCHED_INDEX, SCHED_PERIAPSIS, SCHED_BUCKETS = 0, 1, 1024
+NOALLOC_MAX_LANES = 1 << 21
 GRID_F64, GRID_F32 = 0, 1
 MAX_SPACETIMES = 64
 
@@ -127,6 +128,10 @@ EXPORTS = {
                                             C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                             C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
                                             C.c_void_p]),
+    "malbec_integrate_adaptive_noalloc": (C.c_int, [C.POINTER(c_adaptive), C.POINTER(c_batch),
+                                                    C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                                                    C.c_void_p, C.c_void_p, C.c_void_p,
+                                                    C.c_void_p]),
     "malbec_adaptive_order": (C.c_int, [C.POINTER(c_batch), C.c_int64, C.c_void_p, C.c_void_p,
                                         C.c_void_p, C.c_double, C.c_void_p, C.c_void_p,
                                         C.c_void_p, C.c_size_t, C.c_void_p]),
@@ -373,6 +378,35 @@ def integrate_adaptive(state: torch.Tensor, tau: torch.Tensor, h: torch.Tensor,
                                            _ptr(rejects, torch.int32, n, "rejects"),
                                            _ptr(ws), ws.numel() if ws is not None else 0,
                                            _stream()))
+
+
+def integrate_adaptive_noalloc(state: torch.Tensor, tau: torch.Tensor, h: torch.Tensor,
+                               status: torch.Tensor, steps: torch.Tensor, rejects: torch.Tensor,
+                               spacetimes, tau_end: float, rtol: float = 1e-10,
+                               atol: float = 1e-10, fac: float = 0.9, facmin: float = 0.2,
+                               facmax: float = 5.0, max_attempts: int = 1 << 20,
+                               horizon_factor: float = 1.01, r_escape: float = 1500.0,
+                               block: int = 0, persistent: bool = True, steps_per_chunk: int = 0,
+                               st_of_lane: Optional[torch.Tensor] = None,
+                               schedule: Optional[str] = None):
+    """integrate_adaptive without a workspace: the library's static scratch serves the
+    work queue and the work order (n <= NOALLOC_MAX_LANES; calls that overlap on one GPU
+    race).  Allocates nothing."""
+    n = state.shape[-1]
+    if schedule is None:
+        schedule = "periapsis" if persistent else "index"
+    sched = {"index": SCHED_INDEX, "periapsis": SCHED_PERIAPSIS}[schedule]
+    ad = c_adaptive(tau_end, rtol, atol, fac, facmin, facmax, max_attempts, horizon_factor,
+                    r_escape, block, int(persistent), steps_per_chunk, sched)
+    b = _Batch(_spacetimes(spacetimes), st_of_lane, n)
+    _check(lib().malbec_integrate_adaptive_noalloc(C.byref(ad), C.byref(b.c), n,
+                                                   _ptr(state, torch.float64, 8 * n, "state"),
+                                                   _ptr(tau, torch.float64, n, "tau"),
+                                                   _ptr(h, torch.float64, n, "h"),
+                                                   _ptr(status, torch.int32, n, "status"),
+                                                   _ptr(steps, torch.int32, n, "steps"),
+                                                   _ptr(rejects, torch.int32, n, "rejects"),
+                                                   _stream()))
 
 
 @dataclass

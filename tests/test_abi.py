@@ -236,6 +236,21 @@ def test_adaptive_argument_errors(m, kw, expect):
     assert m.workspace_bytes(m.OP_ADAPTIVE, 10, 1) >= 8
 
 
+def test_adaptive_noalloc_limits(m):
+    """The no-allocation adaptive entry point refuses batches beyond its static scratch
+    and a NULL control block before touching the device."""
+    ad = _adaptive(m, persistent=1, schedule=1)
+    arr, b = _batch(m)
+    fn = m.lib().malbec_integrate_adaptive_noalloc
+    big = m.NOALLOC_MAX_LANES + 1
+    assert fn(C.byref(ad), C.byref(b), big, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, None) == -1
+    assert "no-allocation scratch" in m.last_error()
+    assert fn(None, C.byref(b), 4, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, None) == -1
+    # the scratch holds the workspace of the largest batch it accepts
+    assert m.workspace_bytes(m.OP_ADAPTIVE, m.NOALLOC_MAX_LANES, 2) == (
+        256 + 2 * 4 * m.SCHED_BUCKETS + 8 * m.NOALLOC_MAX_LANES)
+
+
 def test_adaptive_order_workspace_and_argument_errors(m):
     """Workspace of the periapsis schedule (bucket counts and offsets, keys, order) and the
     argument checks of malbec_adaptive_order, none of which touches the device."""
