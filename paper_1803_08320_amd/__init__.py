@@ -40,13 +40,18 @@ NOALLOC_MAX_LANES = 1 << 21
 GRID_F64, GRID_F32 = 0, 1
 MAX_SPACETIMES = 64
 
-# Algorithmic FP64 flops of one RK4 step of one lane as implemented (static count of
-# csrc/kerr_accel.hpp and csrc/ham_accel.hpp by csrc/flopcount.cpp: add/sub/mul/div 1,
-# fma 2, sincos 2): Christoffel form, and Hamilton's equations.
+# FP64 flops of one RK4 step of one lane (static counts by csrc/flopcount.cpp:
+# add/sub/mul/div 1, fma 2, sincos 2).  Christoffel form: the work of a step is fixed
+# by its direct evaluation (kerr_accel_direct in csrc/kerr_accel.hpp: coefficients, then
+# the contraction), 514; the kernels evaluate the same acceleration regrouped, in 474
+# (FLOPS_PER_STEP_F64_KERNEL).  Hamilton's equations: 336.
 FLOPS_PER_STEP_F64 = 514
+FLOPS_PER_STEP_F64_KERNEL = 474
 FLOPS_PER_STEP_F64_HAM = 336
-# one Dormand-Prince 5(4) attempt (six right-hand sides and the tableau; csrc/dp45.hpp)
+# one Dormand-Prince 5(4) attempt (six right-hand sides and the tableau; csrc/dp45.hpp),
+# direct evaluation of the acceleration, and as the kernel evaluates it
 FLOPS_PER_ATTEMPT_DP45 = 1024
+FLOPS_PER_ATTEMPT_DP45_KERNEL = 964
 
 
 class MalbecError(RuntimeError):

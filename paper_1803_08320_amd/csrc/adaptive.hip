@@ -69,7 +69,7 @@ struct AdProg {
     };
     __device__ __forceinline__ void deriv0(Lane &L)
     {
-        AccelF64 f{L.S.M, L.S.a, {0.0, 0.0, 1.0}};
+        AccelF64 f{L.S.M, L.S.a, {}};
         for (int c = 0; c < 4; ++c) L.k1.u[c] = L.y[4 + c];
         f(0, L.y[1], L.y[2], L.y[4], L.y[5], L.y[6], L.y[7], L.k1.acc[0], L.k1.acc[1], L.k1.acc[2],
           L.k1.acc[3]);
@@ -119,7 +119,7 @@ struct AdProg {
             last = true;
         }
         // stage 0 of the rotation base is the start point: sin and cos evaluated fresh
-        AccelF64 f{L.S.M, L.S.a, {0.0, 0.0, 1.0}};
+        AccelF64 f{L.S.M, L.S.a, {}};
         {
             double s, c;
             f.trig(0, L.y[2], s, c);

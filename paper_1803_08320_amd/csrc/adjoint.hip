@@ -134,7 +134,7 @@ __device__ __forceinline__ void jt(const Spacetime &S, const double Y[6], const 
 // rk4_stages).
 __device__ __forceinline__ void vjp_step(const Spacetime &S, double h, const double y[8], double lam[8])
 {
-    AccelF64 f{S.M, S.a, {0.0, 0.0, 1.0}};
+    AccelF64 f{S.M, S.a, {}};
     const double hh = 0.5 * h;
     double Y1[6] = {y[1], y[2], y[4], y[5], y[6], y[7]};
     double at, ar, ath, aph;

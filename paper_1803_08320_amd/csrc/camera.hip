@@ -64,7 +64,7 @@ __device__ __forceinline__ int32_t camera_step(const CamArgs &A, double y[8], in
     const double q = fma(fma(-A.h_r0, q0, y[1]), A.inv_h_r0, q0);
     const double h = A.h0 * fmax(1.0, q);
     double y1[8], sr[3];
-    rk4_step_f64(A.S, h, y, y1, sr);
+    rk4_step_f64<false>(A.S, h, y, y1, sr);
     ++n;
     if (sr[0] <= A.S.r_stop || sr[1] <= A.S.r_stop || sr[2] <= A.S.r_stop) return kHorizon;
     if (!usable(y1)) return kNonfinite;

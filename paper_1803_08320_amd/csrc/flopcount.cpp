@@ -1,12 +1,15 @@
-// Static operation count of one FP64 RK4 step as implemented (host tool).
+// Static operation count of one FP64 RK4 step (host tool).
 //
-// Instantiates the same templates the kernels use (kerr_accel.hpp for the
-// Christoffel form, ham_accel.hpp for Hamilton's equations) with a counting scalar
-// type.  Counting rule: add, sub, mul, div = 1 flop each,
-// fma = 2 flops, sincos = 2 (two results), negation = 0.  The count is
-// independent of the data (the code is straight-line), so one evaluation gives
-// the algorithmic flops per lane-step used for the roofline.  sin/cos of a stage
-// angle count 2 however the kernel obtains them (library sincos or rotation).
+// Instantiates the templates the kernels use (kerr_accel.hpp for the Christoffel
+// form, ham_accel.hpp for Hamilton's equations, dp45.hpp for the adaptive pair) with a
+// counting scalar type.  Counting rule: add, sub, mul, div = 1 flop each, fma = 2
+// flops, sincos = 2 (two results), negation = 0.  The count is independent of the
+// data (the code is straight-line), so one evaluation gives the flops per lane-step.
+// sin/cos of a stage angle count 2 however the kernel obtains them (library sincos or
+// rotation).  The Christoffel form is counted twice: in its direct form
+// (kerr_accel_direct: the coefficients, then the contraction), which fixes the work of
+// one step for the roofline, and in the regrouped form the kernels evaluate
+// (kerr_accel), which needs fewer operations for the same acceleration.
 //   g++ -O0 -std=c++17 flopcount.cpp -o flopcount && ./flopcount
 #include <cstdio>
 
@@ -34,6 +37,7 @@ inline Counted recip(Counted x) { ++g_div; g_flops += 1; return Counted(1.0 / x.
 #include "ham_accel.hpp"
 #include "kerr_accel.hpp"
 
+template <bool DIRECT>
 struct AccelCount {
     Counted M, a;
     void operator()(int, Counted r, Counted th, Counted ut, Counted ur, Counted uth, Counted uph,
@@ -41,7 +45,10 @@ struct AccelCount {
     {
         g_flops += 2;  // sincos
         Counted s(std::sin(th.v)), c(std::cos(th.v));
-        malbec::kerr_accel<Counted>(M, a, r, s, c, ut, ur, uth, uph, at, ar, ath, aph);
+        if (DIRECT)
+            malbec::kerr_accel_direct<Counted>(M, a, r, s, c, ut, ur, uth, uph, at, ar, ath, aph);
+        else
+            malbec::kerr_accel<Counted>(M, a, r, s, c, ut, ur, uth, uph, at, ar, ath, aph);
     }
 };
 
@@ -57,22 +64,41 @@ struct HamCount {
     }
 };
 
-int main()
+template <bool DIRECT>
+void count_christoffel(const char *tag)
 {
     Counted y[8] = {0.0, 7.0, 1.1, 0.0, 1.2, 0.1, 0.02, 0.05}, y1[8], sr[3];
-    AccelCount f{Counted(1.0), Counted(0.9)};
+    AccelCount<DIRECT> f{Counted(1.0), Counted(0.9)};
     Counted at, ar, ath, aph;
     g_flops = g_div = g_fma = g_addmul = 0;
     f(0, y[1], y[2], y[4], y[5], y[6], y[7], at, ar, ath, aph);
     long rhs = g_flops, rhs_div = g_div, rhs_fma = g_fma, rhs_am = g_addmul;
     g_flops = g_div = g_fma = g_addmul = 0;
     malbec::rk4_step(f, Counted(0.02), y, y1, sr);
-    std::printf("rhs_flops %ld\nrhs_div %ld\nrhs_fma %ld\nrhs_addmul %ld\nstep_flops %ld\nstep_fma %ld\nstep_addmul %ld\nstep_div %ld\n",
-                rhs, rhs_div, rhs_fma, rhs_am, g_flops, g_fma, g_addmul, g_div);
+    std::printf("rhs_flops%s %ld\nrhs_div%s %ld\nrhs_fma%s %ld\nrhs_addmul%s %ld\n", tag, rhs, tag,
+                rhs_div, tag, rhs_fma, tag, rhs_am);
+    std::printf("step_flops%s %ld\nstep_fma%s %ld\nstep_addmul%s %ld\nstep_div%s %ld\n", tag,
+                g_flops, tag, g_fma, tag, g_addmul, tag, g_div);
+    // one Dormand-Prince attempt (six right-hand sides, the stage points, the
+    // 5th-order result and the error estimate; the controller's few operations and
+    // the pow are not counted)
+    malbec::Deriv<Counted> k1, k7;
+    for (int c = 0; c < 4; ++c) k1.u[c] = y[4 + c];
+    f(0, y[1], y[2], y[4], y[5], y[6], y[7], k1.acc[0], k1.acc[1], k1.acc[2], k1.acc[3]);
+    Counted e[8], sr5[5];
+    g_flops = g_div = g_fma = g_addmul = 0;
+    malbec::dp45_attempt(f, Counted(0.02), y, k1, y1, e, k7, sr5);
+    std::printf("dp45_attempt_flops%s %ld\n", tag, g_flops);
+}
+
+int main()
+{
+    count_christoffel<true>("");          // direct form: the roofline's work per step
+    count_christoffel<false>("_kernel");  // regrouped form the kernels evaluate
 
     // Hamilton's equations: z = (t, r, theta, phi, p_t, p_r, p_theta, p_phi); the
     // products a p_t, a p_phi are formed once per lane, not per step
-    Counted z[8] = {0.0, 7.0, 1.1, 0.0, -0.95, 0.1, 0.3, 3.0}, z1[8];
+    Counted z[8] = {0.0, 7.0, 1.1, 0.0, -0.95, 0.1, 0.3, 3.0}, z1[8], sr[3];
     HamCount hf{Counted(1.0), Counted(0.9),
                 malbec::HamConst<Counted>{z[4], z[7], Counted(0.9 * z[4].v), Counted(0.9 * z[7].v)}};
     Counted dt, dr, dth, dph, dpr, dpth;
@@ -83,16 +109,5 @@ int main()
     malbec::rk4_ham_step(hf, Counted(0.02), z, z1, sr);
     std::printf("ham_rhs_flops %ld\nham_step_flops %ld\nham_step_fma %ld\nham_step_addmul %ld\nham_step_div %ld\n",
                 hrhs, g_flops, g_fma, g_addmul, g_div);
-
-    // one Dormand-Prince attempt (six right-hand sides, the stage points, the
-    // 5th-order result and the error estimate; the controller's few operations and
-    // the pow are not counted)
-    malbec::Deriv<Counted> k1, k7;
-    for (int c = 0; c < 4; ++c) k1.u[c] = y[4 + c];
-    f(0, y[1], y[2], y[4], y[5], y[6], y[7], k1.acc[0], k1.acc[1], k1.acc[2], k1.acc[3]);
-    Counted e[8], sr5[5];
-    g_flops = g_div = g_fma = g_addmul = 0;
-    malbec::dp45_attempt(f, Counted(0.02), y, k1, y1, e, k7, sr5);
-    std::printf("dp45_attempt_flops %ld\n", g_flops);
     return 0;
 }

@@ -87,26 +87,33 @@ __global__ void __launch_bounds__(256) rk4_f64_kernel(IntArgs A, StTable T)
 
     if (!CKPT && st == kActive) {
         // Two steps per iteration, the second with the roles of y and y1 swapped, so
-        // that an accepted step never copies the state.
+        // that an accepted step never copies the state.  The common outcome of the stop
+        // rules is tested first.  A launch always has n_steps >= 1 (the launcher makes
+        // none for a call of zero steps).
         double y1[8];
-        while (taken < A.n_steps) {
+        int32_t ks = 0;
+        for (;;) {
             double sr[3];
-            bool accept;
+            bool accept = true;
             step_f64<HAM>(S, P, A.h, y, y1, sr);
-            ++taken;
-            st = terminate_f64(S, A.r_escape, sr, y1, accept);
-            if (st != kActive || taken == A.n_steps) {
+            ++ks;
+            if (!still_active_f64(S, A.r_escape, sr, y1))
+                st = terminate_f64(S, A.r_escape, sr, y1, accept);
+            if (st != kActive || ks == A.n_steps) {
                 if (accept) copy8(y, y1);
                 break;
             }
             step_f64<HAM>(S, P, A.h, y1, y, sr);
-            ++taken;
-            st = terminate_f64(S, A.r_escape, sr, y, accept);
-            if (st != kActive) {
+            ++ks;
+            accept = true;
+            if (!still_active_f64(S, A.r_escape, sr, y))
+                st = terminate_f64(S, A.r_escape, sr, y, accept);
+            if (st != kActive || ks == A.n_steps) {
                 if (!accept) copy8(y, y1);
                 break;
             }
         }
+        taken = ks;
         // the lane's index rebuilt from wave-uniform values and its position in the
         // wavefront: no per-lane address stays live across the loop
         const int64_t ie = (int64_t)blockIdx.x * blockDim.x + wave0 +

@@ -35,7 +35,11 @@ struct Spacetime {
 // so the addition does not cancel; cos is accurate in absolute terms, which is how the
 // right-hand sides use it).  At the step sizes of the workloads (h <= 0.1 with
 // |u^theta| well below 1) stage points stay within 0.04 of the step's start.
+// SHORT: sin d through d^5 and cos d through d^6 for |d| <= kRotMaxShort, where the
+// truncation is below 2e-18 absolute (d^7 / 7!) and 3e-21 (d^8 / 8!): with
+// sin(theta) >= 2 |d| that is below 1.1e-16 relative in sin(theta + d).
 constexpr double kRotMax = 0.04;
+constexpr double kRotMaxShort = 0.01;
 
 // a * b + c as one three-address v_fma_f64 with the constant addend c read from a
 // scalar register pair.  Used for the polynomial steps below: the compiler's own
@@ -55,17 +59,24 @@ __device__ __forceinline__ double fma3c(double a, double b, double c)
 constexpr double kF2 = 1.0 / 2.0, kF3 = 1.0 / 6.0, kF4 = 1.0 / 24.0, kF5 = 1.0 / 120.0,
                  kF6 = 1.0 / 720.0, kF7 = 1.0 / 5040.0, kF8 = 1.0 / 40320.0;
 
+template <bool SHORT = false>
 __device__ __forceinline__ void rotate(double s0, double c0, double d, double &s, double &c)
 {
     const double d2 = d * d;
     // sin d = d + d^3 ps(d^2),  cos d = 1 - d^2 pc(d^2)
-    double ps = fma3c(d2, -kF7, kF5);
-    ps = fma3c(d2, ps, -kF3);
+    double ps, pc;
+    if (SHORT) {
+        ps = fma3c(d2, kF5, -kF3);
+        pc = fma3c(d2, -kF6, kF4);
+    } else {
+        ps = fma3c(d2, -kF7, kF5);
+        ps = fma3c(d2, ps, -kF3);
+        pc = fma3c(d2, -kF8, kF6);
+        pc = fma3c(d2, pc, -kF4);
+    }
+    pc = fma(d2, pc, SHORT ? -kF2 : kF2);
     const double sd = fma(d * d2, ps, d);
-    double pc = fma3c(d2, -kF8, kF6);
-    pc = fma3c(d2, pc, -kF4);
-    pc = fma(d2, pc, kF2);
-    const double cd = fma(-d2, pc, 1.0);
+    const double cd = SHORT ? fma(d2, pc, 1.0) : fma(-d2, pc, 1.0);
     s = fma(s0, cd, c0 * sd);
     c = fma(c0, cd, -s0 * sd);
 }
@@ -106,8 +117,12 @@ __device__ __forceinline__ void sincos_0pi(double th, double &s, double &c)
 {
     double sx, cx;
     const double k = sincos_reduce(th, sx, cx);
-    s = k == 1.0 ? cx : (k == 0.0 ? sx : -sx);
-    c = k == 1.0 ? -sx : (k == 0.0 ? cx : -cx);
+    // (s, c) = A (sx, cx) + B (cx, -sx) with (A, B) = (1 - k, k (2 - k)): (1, 0), (0, 1)
+    // and (-1, 0) for k = 0, 1, 2 (products by 0 and +-1 and sums with 0 are exact)
+    const double A = 1.0 - k;
+    const double B = k * (2.0 - k);
+    s = fma(A, sx, B * cx);
+    c = fma(A, cx, -B * sx);
 }
 
 // sin and cos of any moderate theta (|theta| < 1e6; stage points may leave (0, pi)):
@@ -121,34 +136,58 @@ __device__ __forceinline__ void sincos_any(double th, double &s, double &c)
     c = ((q + 1) & 2) ? -cc : cc;
 }
 
-// sin and cos of the theta of RK4 stage `stage`.  Stage 0 evaluates them and keeps
-// (theta, sin, cos); the later stages of the same step, whose theta differs from the
-// stage-0 theta by an exactly computed small d, rotate that pair instead (a fresh
-// evaluation if |d| > kRotMax, or if the step brings theta close to a pole, where the
-// rotation's cancellation would cost relative accuracy in sin theta).
-struct StageTrig {
-    double th0, s0, c0, lim;
-    __device__ __forceinline__ void operator()(int stage, double th, double &s, double &c)
+// Reference angle of the stage rotations: theta_b with its sin and cos (a fresh
+// evaluation) and the largest |d| = |theta - theta_b| that the rotation by d may take
+// from it, min(kRotMax, sin(theta_b) / 2) (kRotMaxShort with the SHORT polynomials).
+template <bool SHORT>
+struct TrigBase {
+    double th, s, c, lim;
+    __device__ __forceinline__ void set(double theta)
     {
-        const double d = th - th0;
-        if (stage == 0) {
-            sincos_0pi(th, s, c);
-            th0 = th;
-            s0 = s;
-            c0 = c;
-            lim = fmin(kRotMax, 0.5 * s);
-        } else if (!(fabs(d) <= lim)) {
-            sincos_any(th, s, c);
-        } else {
-            rotate(s0, c0, d, s, c);
-        }
+        sincos_0pi(theta, s, c);
+        th = theta;
+        lim = fmin(SHORT ? kRotMaxShort : kRotMax, 0.5 * s);
+    }
+    // sin and cos of theta: the base pair rotated by the exactly computed d = theta -
+    // theta_b, or a fresh evaluation when |d| exceeds the limit (a stage far from the
+    // base, or a base close to a pole, where the rotation's cancellation would cost
+    // relative accuracy in sin theta).
+    __device__ __forceinline__ void at(double theta, double &so, double &co) const
+    {
+        const double d = theta - th;
+        rotate<SHORT>(s, c, d, so, co);
+        if (!(fabs(d) <= lim)) sincos_any(theta, so, co);
     }
 };
 
+// sin and cos of the theta of RK4 stage `stage`: stage 0 evaluates them afresh at the
+// step's own theta and keeps them as the base; the later stages of the same step rotate
+// that pair, so the trigonometry of a step depends on the step's start state alone (and
+// rotations never chain from step to step).  SHORT: the short rotation polynomials,
+// for fixed steps whose stage points stay within h |u^theta| <= 0.01 of the start (the
+// Kerr bound-orbit workloads at h = 0.02: below 0.004); larger offsets fall back to a
+// fresh evaluation.
+template <bool SHORT>
+struct StageTrigT {
+    TrigBase<SHORT> B;
+    __device__ __forceinline__ void operator()(int stage, double th, double &s, double &c)
+    {
+        if (stage == 0) {
+            B.set(th);
+            s = B.s;
+            c = B.c;
+        } else {
+            B.at(th, s, c);
+        }
+    }
+};
+using StageTrig = StageTrigT<false>;
+
 // FP64 geodesic acceleration (Christoffel form) as a functor for rk4_stages.
-struct AccelF64 {
+template <typename Trig>
+struct AccelF64T {
     double M, a;
-    StageTrig trig;
+    Trig trig;
     __device__ __forceinline__ void operator()(int stage, double r, double th, double ut, double ur,
                                                double uth, double uph, double &at, double &ar,
                                                double &ath, double &aph)
@@ -158,19 +197,25 @@ struct AccelF64 {
         kerr_accel<double>(M, a, r, s, c, ut, ur, uth, uph, at, ar, ath, aph);
     }
 };
+using AccelF64 = AccelF64T<StageTrig>;
 
+// One FP64 RK4 step (Christoffel form).  SHORT = true for the fixed-step integrators
+// (small stage offsets), false for steps whose stage points move further (the camera's
+// h = h0 max(1, r / h_r0)).
+template <bool SHORT = true>
 __device__ __forceinline__ void rk4_step_f64(const Spacetime &S, double h, const double y[8],
                                              double y1[8], double sr[3])
 {
-    AccelF64 f{S.M, S.a, {0.0, 0.0, 1.0}};
+    AccelF64T<StageTrigT<SHORT>> f{S.M, S.a, {}};
     rk4_step(f, h, y, y1, sr);
 }
 
 // FP64 canonical right-hand side (Hamiltonian form) as a functor for rk4_ham_step.
-struct HamF64 {
+template <typename Trig>
+struct HamF64T {
     double M, a;
     const HamConst<double> &P;
-    StageTrig trig;
+    Trig trig;
     __device__ __forceinline__ void operator()(int stage, double r, double th, double pr, double pth,
                                                double &dt, double &dr, double &dth, double &dph,
                                                double &dpr, double &dpth)
@@ -185,7 +230,7 @@ __device__ __forceinline__ void rk4_step_ham_f64(const Spacetime &S, const HamCo
                                                  double h, const double z[8], double z1[8],
                                                  double sr[3])
 {
-    HamF64 f{S.M, S.a, P, {0.0, 0.0, 1.0}};
+    HamF64T<StageTrigT<true>> f{S.M, S.a, P, {}};
     rk4_ham_step(f, h, z, z1, sr);
 }
 
@@ -211,6 +256,23 @@ __device__ __forceinline__ int32_t terminate_f64(const Spacetime &S, double r_es
     if (y1[1] <= S.r_stop) return kHorizon;
     if (y1[1] >= r_escape) return kEscape;
     return kActive;
+}
+
+// The common outcome of terminate_f64 tested first: true only when it would return
+// kActive with y1 accepted (every stage radius above r_stop, y1's r inside
+// (r_stop, r_escape) and theta inside (0, pi), which rule out a NaN there, and the
+// other six components finite).  When it returns false (a NaN stage radius included)
+// the caller applies terminate_f64, which may still give kActive.
+__device__ __forceinline__ bool still_active_f64(const Spacetime &S, double r_escape,
+                                                 const double sr[3], const double y1[8])
+{
+    bool ok = sr[0] > S.r_stop && sr[1] > S.r_stop && sr[2] > S.r_stop;
+    ok = ok && y1[1] > S.r_stop && y1[1] < r_escape;
+    ok = ok && y1[2] > 0.0 && y1[2] < 3.14159265358979323846;
+    ok = ok && __builtin_isfinite(y1[0]) && __builtin_isfinite(y1[3]);
+#pragma unroll
+    for (int k = 4; k < 8; ++k) ok = ok && __builtin_isfinite(y1[k]);
+    return ok;
 }
 
 }  // namespace malbec

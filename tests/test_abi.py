@@ -297,7 +297,8 @@ def test_grid_argument_errors(m, kw, run_kw, expect):
 
 
 def test_flop_count_constant(m, tmp_path):
-    """The roofline's flops per lane-step equal the static count of the templates the
+    """The roofline's flops per lane-step equal the static count of the templates: the
+    direct evaluation of the acceleration (the work of a step) and the regrouped one the
     kernels instantiate."""
     exe = tmp_path / "flopcount"
     src = os.path.join(ROOT, "paper_1803_08320_amd", "csrc", "flopcount.cpp")
@@ -305,8 +306,12 @@ def test_flop_count_constant(m, tmp_path):
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
     vals = dict(l.split() for l in out.strip().split("\n"))
     assert int(vals["step_flops"]) == m.FLOPS_PER_STEP_F64
+    assert int(vals["step_flops_kernel"]) == m.FLOPS_PER_STEP_F64_KERNEL
     assert int(vals["ham_step_flops"]) == m.FLOPS_PER_STEP_F64_HAM
     assert int(vals["dp45_attempt_flops"]) == m.FLOPS_PER_ATTEMPT_DP45
+    assert int(vals["dp45_attempt_flops_kernel"]) == m.FLOPS_PER_ATTEMPT_DP45_KERNEL
+    # the regrouped evaluation needs fewer operations than the direct one
+    assert int(vals["rhs_flops_kernel"]) < int(vals["rhs_flops"])
 
 
 def test_missing_library_and_host_tensors_fail_loudly(m, monkeypatch):
