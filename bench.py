@@ -30,6 +30,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_FP64_VECTOR_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 128 FP64 flop/clk/CU
+# 256 CU x 2.4 GHz x 256 FP32 flop/clk/CU: the published vector FP32 figure, reached
+# here without packed instructions (a wave64 FP32 VALU instruction issues in about half
+# the clocks of an FP64 one, counters of the FP32-compensated kernel)
+PEAK_FP32_VECTOR_TFLOPS = 157.3
 
 # HBM traffic of one rk4_f64_kernel launch of this workload, from rocprofv3 counter
 # runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by the ratio of a
@@ -39,8 +43,8 @@ PEAK_FP64_VECTOR_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 128 FP64 flop/clk/CU
 # taken again.
 KERNEL_SOURCES = ("integrate.hip", "kerr_device.hpp", "kerr_accel.hpp", "ham_accel.hpp",
                   "persistent.hpp")
-TRAFFIC = {"sources_sha256": "e2afb9f2394e0fdef23cb374a6b1a77de0e58effb2c8898fcde05c13885e27c6",
-           "fetch_kib": 36950.4375, "fetch_scale": 1048576 / 524307.5625,
+TRAFFIC = {"sources_sha256": "d5cbb2d80a961867e0fd094a668bf39d5de7cd6bdce03ee0df67239f519950a7",
+           "fetch_kib": 36941.5, "fetch_scale": 1048576 / 524307.6875,
            "write_kib": 73728.0, "write_scale": 1048576 / 1048576.0}
 
 
@@ -271,12 +275,14 @@ def main():
         state.copy_(s0)
         status.zero_()
         steps.zero_()
+        ev32 = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
         torch.cuda.synchronize()
-        t = time.perf_counter()
+        ev32[0].record()
         m.integrate(state, status, steps, st, h=h, n_steps=n_rk, precision="f32k",
                     fp64_zone_factor=1.2, block=args.block)
+        ev32[1].record()
         torch.cuda.synchronize()
-        dt = time.perf_counter() - t
+        dt = ev32[0].elapsed_time(ev32[1]) / 1e3
         k_steps = int(steps.sum().item())
         m.invariants(state, st, out=inv1)
         j1 = inv1.cpu().numpy()
@@ -292,7 +298,15 @@ def main():
                              y[1] * np.cos(y[2])])
         pos = (np.linalg.norm(cart(a32) - cart(a64), axis=0) / a64[1])[act32]
         v32 = k_steps / dt
+        ach32 = m.FLOPS_PER_STEP_F32K * v32 / 1e12
         result["f32k"] = {"value": v32, "unit": "lane-steps/s", "speedup_vs_f64": v32 / result["value"],
+                          "kernel_ms": 1e3 * dt,
+                          "roofline": {"bound": "alu", "achieved": ach32,
+                                       "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                                       "frac": ach32 / PEAK_FP32_VECTOR_TFLOPS,
+                                       "flops_per_lane_step": m.FLOPS_PER_STEP_F32K,
+                                       "kernel_flops_per_lane_step": m.FLOPS_PER_STEP_F32K_KERNEL,
+                                       "dtype": "f32 stages, f32 pair state"},
                           "zone": "FP64 steps inside 1.2 r_+",
                           "dE_over_E_p99": float(np.quantile(dE32, 0.99)),
                           "dQ_over_Q_p99": float(np.quantile(dQ32, 0.99)),
@@ -363,10 +377,15 @@ def main():
         acth = (status == 0).cpu().numpy() & act
         qh = acth & (i0[2] >= 0.1)
         dQh = np.abs(j1[2] / i0[2] - 1)[qh]
+        achh32 = m.FLOPS_PER_STEP_F32K_HAM * hk_steps / dt / 1e12
         result["f32k_hamiltonian"] = {
             "value": hk_steps / dt, "unit": "lane-steps/s",
             "speedup_vs_f64_christoffel": hk_steps / dt / result["value"],
-            "kernel_ms": 1e3 * dt, "zone": "FP64 steps inside 1.2 r_+",
+            "kernel_ms": 1e3 * dt,
+            "roofline": {"bound": "alu", "achieved": achh32, "peak": PEAK_FP32_VECTOR_TFLOPS,
+                         "unit": "TFLOP/s", "frac": achh32 / PEAK_FP32_VECTOR_TFLOPS,
+                         "flops_per_lane_step": m.FLOPS_PER_STEP_F32K_HAM},
+            "zone": "FP64 steps inside 1.2 r_+",
             "dE_over_E_max": float(np.abs(j1[0] / i0[0] - 1)[acth].max()),
             "dQ_over_Q_p99": float(np.quantile(dQh, 0.99)),
             "dQ_over_Q_max": float(dQh.max())}

@@ -64,6 +64,10 @@ struct HamCount {
     }
 };
 
+// flops of the compensated update of one component: d + lo, then the two-sum of hi and
+// that (s = a + b, b' = s - a, a' = s - b', e = (a - a') + (b - b'): six additions)
+constexpr long kCompensated = 7;
+
 template <bool DIRECT>
 void count_christoffel(const char *tag)
 {
@@ -79,6 +83,12 @@ void count_christoffel(const char *tag)
                 rhs_div, tag, rhs_fma, tag, rhs_am);
     std::printf("step_flops%s %ld\nstep_fma%s %ld\nstep_addmul%s %ld\nstep_div%s %ld\n", tag,
                 g_flops, tag, g_fma, tag, g_addmul, tag, g_div);
+    // the FP32-compensated step: the increment h/6 (k1 + 2 k2 + 2 k3 + k4), then per
+    // component d + lo and Knuth's two-sum with hi (6 additions): kCompensated
+    g_flops = g_div = g_fma = g_addmul = 0;
+    Counted d[8];
+    malbec::rk4_delta(f, Counted(0.02), y, d, sr);
+    std::printf("f32k_step_flops%s %ld\n", tag, g_flops + 8 * kCompensated);
     // one Dormand-Prince attempt (six right-hand sides, the stage points, the
     // 5th-order result and the error estimate; the controller's few operations and
     // the pow are not counted)
@@ -109,5 +119,9 @@ int main()
     malbec::rk4_ham_step(hf, Counted(0.02), z, z1, sr);
     std::printf("ham_rhs_flops %ld\nham_step_flops %ld\nham_step_fma %ld\nham_step_addmul %ld\nham_step_div %ld\n",
                 hrhs, g_flops, g_fma, g_addmul, g_div);
+    g_flops = g_div = g_fma = g_addmul = 0;
+    Counted dz[8];
+    malbec::rk4_ham_delta(hf, Counted(0.02), z, dz, sr);
+    std::printf("f32k_ham_step_flops %ld\n", g_flops + 8 * kCompensated);
     return 0;
 }

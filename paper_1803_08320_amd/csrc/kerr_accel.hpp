@@ -151,17 +151,23 @@ MALBEC_HD inline void kerr_contract(const KerrCoef<T> &K, T ut, T ur, T uth, T u
 // du^mu/dtau for the 4-velocity (ut, ur, uth, uph) at (r, theta) with s = sin theta,
 // c = cos theta.  T = double or float.  The same acceleration as kerr_contract with the
 // coefficients of kerr_coef (the direct form, which the adjoint differentiates),
-// regrouped so that fewer intermediate products are formed:
-//  - the (t, phi) partials enter through V = u^t - a s^2 u^phi:
-//      (1/2)(d_r g_tb) u^b = (1/2) d_r q V,
-//      (1/2)(d_r g_pb) u^b = -a s^2 (1/2)(d_r g_tb) u^b + r s^2 u^phi,
-//      (1/2)(d_th g_tb) u^b = (1/2) d_th q V - a q s c u^phi,
-//      (1/2)(d_th g_pb) u^b = -a (1/2) d_th(q s^2) V + (g_pp / s^2) s c u^phi;
-//  - g^rr = Delta / rho^2 and g^thth = 1 / rho^2 are folded into the r and theta
-//    coefficients (with (1/2) d_th g_rr = -a^2 s c / Delta):
-//      g^rr (1/2) d_r g_rr = r / rho^2 - (r - M) / Delta,
-//      g^rr (1/2) d_th g_rr = -a^2 s c / rho^2 = -g^thth a^2 s c,
-//      g^thth (1/2) d_th g_rr = -a^2 s c / (rho^2 Delta).
+// regrouped so that fewer intermediate products are formed.  With V = u^t - a s^2 u^phi
+// and A = r^2 + a^2, the half partials of the (t, phi) metric components contracted
+// with u^b are
+//   (1/2)(d_r g_tb) u^b = (1/2) d_r q V,   (1/2)(d_th g_tb) u^b = (1/2) d_th q V - a q s c u^phi,
+//   (1/2)(d_l g_pb) u^b = -a s^2 (1/2)(d_l g_tb) u^b + X_l,
+//   X_r = r s^2 u^phi,   X_th = -a q s c V + A s c u^phi,
+// so with Wt = u^l (1/2)(d_l g_tb) u^b and Y = u^r X_r + u^theta X_th the lowered
+// accelerations are F_t = -2 Wt, F_phi = -2 (-a s^2 Wt + Y), and the block inverse of the
+// (t, phi) metric (determinant -Delta s^2) raises them to
+//   a^t = (2 / Delta) (A Wt + a q Y),   a^phi = (2 a / Delta) Wt + (2 (q - 1) / (Delta s^2)) Y
+// (g_phiphi and g_tphi cancel out of both).  g^rr = Delta / rho^2 and g^thth = 1 / rho^2
+// are folded into the r and theta coefficients (with (1/2) d_th g_rr = -a^2 s c / Delta):
+//   a^r = (Delta / rho^2)(Qr + r (u^theta)^2) + (a^2 s c / rho^2) 2 u^r u^theta
+//         - (r / rho^2 - (r - M) / Delta) (u^r)^2,
+//   a^theta = (Qth - 2 r u^r u^theta) / rho^2 + (a^2 s c / rho^2)((u^theta)^2 - (u^r)^2 / Delta),
+// Q_l = u^t (1/2)(d_l g_tb) u^b + u^phi (1/2)(d_l g_pb) u^b = (1/2)(d_l g_tb) u^b V + u^phi X_l
+// being the (t, phi) part of (1/2)(d_l g_ab) u^a u^b.
 template <typename T>
 MALBEC_HD inline void kerr_accel(T M, T a, T r, T s, T c, T ut, T ur, T uth, T uph, T &at, T &ar,
                                  T &ath, T &aph)
@@ -185,37 +191,25 @@ MALBEC_HD inline void kerr_accel(T M, T a, T r, T s, T c, T ut, T ur, T uth, T u
     const T k1 = (a2 * sc) * irho2;         // a^2 s c / rho^2
     const T hdq_th = q * k1;                // (1/2) d_th q
     const T aq = -a * q;                    // g_tphi / s^2
-    const T gpp_os2 = fma(a2, q * s2, A);   // g_phiphi / s^2
     const T as2n = -a * s2;
     const T aqsc = aq * sc;
 
-    // (1/2) (d_l g_{t b}) u^b and (1/2) (d_l g_{phi b}) u^b for l = r, theta
     const T V = fma(as2n, uph, ut);
-    const T Pt_r = hdq_r * V;
-    const T Pp_r = fma(as2n, Pt_r, (r * s2) * uph);
+    const T Pt_r = hdq_r * V;               // (1/2) (d_r g_tb) u^b
     const T Pt_th = fma(hdq_th, V, aqsc * uph);
-    const T Pp_th = fma(fma(hdq_th, as2n, aqsc), V, (gpp_os2 * sc) * uph);
-
-    // lowered (t, phi) accelerations F_t = -2 Wt, F_phi = -2 Wp, and the (t, phi) parts
-    // of (1/2) (d_r g_ab) u^a u^b and (1/2) (d_th g_ab) u^a u^b
+    const T X_r = (r * s2) * uph;
+    const T X_th = fma(aqsc, V, (A * sc) * uph);
     const T Wt = fma(ur, Pt_r, uth * Pt_th);
-    const T Wp = fma(ur, Pp_r, uth * Pp_th);
-    const T Qr = fma(ut, Pt_r, uph * Pp_r);
-    const T Qth = fma(ut, Pt_th, uph * Pp_th);
+    const T Y = fma(ur, X_r, uth * X_th);
+    const T Qr = fma(Pt_r, V, uph * X_r);
+    const T Qth = fma(Pt_th, V, uph * X_th);
     const T urur = ur * ur, uthuth = uth * uth, uruth2 = (ur + ur) * uth;  // 2 ur uth
 
-    // raise with the (t, phi) block inverse: -(1/2) [[Rtt, -Rtp], [-Rtp, Rpp]]
     const T iDelta2 = iDelta + iDelta;
-    const T Rtt = iDelta2 * gpp_os2;
-    const T Rtp = aq * iDelta2;
-    const T Rpp = iDs2 * fma(T(2), q, T(-2));
-    at = fma(Rtt, Wt, -Rtp * Wp);
-    aph = fma(Rpp, Wp, -Rtp * Wt);
-    // a^r = (Delta / rho^2) (Qr + r uth^2) + (a^2 s c / rho^2) 2 ur uth
-    //       - (r / rho^2 - (r - M) / Delta) ur^2
+    at = iDelta2 * fma(A, Wt, -aq * Y);
+    aph = fma(a * iDelta2, Wt, (iDs2 * fma(T(2), q, T(-2))) * Y);
     const T e_rr = fma(-iDelta, r - M, ri);
     ar = fma(k1, uruth2, fma(-e_rr, urur, (Delta * irho2) * fma(r, uthuth, Qr)));
-    // a^theta = (Qth - r 2 ur uth) / rho^2 + (a^2 s c / rho^2) (uth^2 - ur^2 / Delta)
     ath = fma(irho2, fma(-r, uruth2, Qth), k1 * fma(-iDelta, urur, uthuth));
 }
 

@@ -308,6 +308,9 @@ def test_flop_count_constant(m, tmp_path):
     assert int(vals["step_flops"]) == m.FLOPS_PER_STEP_F64
     assert int(vals["step_flops_kernel"]) == m.FLOPS_PER_STEP_F64_KERNEL
     assert int(vals["ham_step_flops"]) == m.FLOPS_PER_STEP_F64_HAM
+    assert int(vals["f32k_step_flops"]) == m.FLOPS_PER_STEP_F32K
+    assert int(vals["f32k_step_flops_kernel"]) == m.FLOPS_PER_STEP_F32K_KERNEL
+    assert int(vals["f32k_ham_step_flops"]) == m.FLOPS_PER_STEP_F32K_HAM
     assert int(vals["dp45_attempt_flops"]) == m.FLOPS_PER_ATTEMPT_DP45
     assert int(vals["dp45_attempt_flops_kernel"]) == m.FLOPS_PER_ATTEMPT_DP45_KERNEL
     # the regrouped evaluation needs fewer operations than the direct one
