@@ -123,6 +123,13 @@ def main():
     inv0 = torch.empty((4, n), dtype=torch.float64, device="cuda")
     inv1 = torch.empty_like(inv0)
     torch.cuda.synchronize()
+    # launch shape: the autotuner's choice for this batch (timed on a sample before the
+    # timed region, cached), which the integrate calls below take through block = 0
+    if args.block == 0:
+        from paper_1803_08320_amd import autotune
+        shape_block = autotune.integrate_shape(s0, st, h)[0]
+    else:
+        shape_block = args.block
 
     def one_step(ev=None):
         state.copy_(s0)
@@ -178,7 +185,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "kerr_a0.9_bound_timelike_1M_lanes_20000_steps_h0.02_fp64",
                    "lanes": n, "rk4_steps": n_rk, "h": h, "spin": 0.9, "seed": 2,
-                   "block": args.block or 256},
+                   "block": shape_block,
+                   "launch_shape": "autotuned" if args.block == 0 else "fixed by --block"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR_TFLOPS,
                      "traffic": measured_traffic_bytes(), "kernel": "rk4_f64_kernel",
@@ -572,6 +580,7 @@ def main():
 
     if not args.no_extra:
         result["extra"] = extra_legs(m, torch, np)
+        result["schwarzschild"] = schwarzschild_leg(m, torch, np)
 
     if not args.no_cpu_baseline:
         import oracle
@@ -595,6 +604,8 @@ def main():
                                   "cores": nthreads, "kind": "oracle", "cpu_model": cpu_model,
                                   "sample": "%d strided lanes of the workload x %d RK4 steps "
                                             "(%.1f s wall)" % (len(idx), n_rk, dt)}
+        if not args.no_extra:
+            result["cpu_baseline_by_config"] = oracle_configs(oracle, np, nthreads, result)
     print(json.dumps(result))
 
 
@@ -607,10 +618,116 @@ def _timed(torch, fn):
     return time.perf_counter() - t
 
 
+def schwarzschild_leg(m, torch, np):
+    """Schwarzschild M = 1: 1,024 equatorial timelike lanes on circular orbits with
+    r0 in [6.5, 20] and L perturbed by up to 1e-3 relative (seed 1), h = 0.01, 10,000
+    steps, FP64; with the drift of E, L and of the norm from -1.  Too few lanes to fill
+    the chip (16 waves): the rate shown is latency-bound."""
+    st = [(1.0, 0.0)]
+    n = 1024
+    spec = m.ICSpec(mode=m.IC_CIRCULAR, seed=1, r_lo=6.5, r_hi=20.0, dL=1e-3)
+    s0, c0, _ = m.init_particles(spec, st, n)
+    state = torch.empty_like(s0)
+    status, steps = m.new_lane_arrays(n)
+    ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+
+    def run():
+        state.copy_(s0)
+        status.zero_()
+        steps.zero_()
+        ev[0].record()
+        m.integrate(state, status, steps, st, h=0.01, n_steps=10000)
+        ev[1].record()
+    run()
+    run()
+    torch.cuda.synchronize()
+    dt = ev[0].elapsed_time(ev[1]) / 1e3
+    inv = m.invariants(state, st)
+    i0 = m.invariants(s0, st)
+    torch.cuda.synchronize()
+    i0, i1 = i0.cpu().numpy(), inv.cpu().numpy()
+    return {"value": float(steps.sum().item()) / dt, "unit": "lane-steps/s", "kernel_ms": 1e3 * dt,
+            "lanes": n, "rk4_steps": 10000, "h": 0.01,
+            "dE_over_E_max": float(np.abs(i1[0] / i0[0] - 1).max()),
+            "dL_over_L_max": float(np.abs(i1[1] / i0[1] - 1).max()),
+            "norm_drift_max": float(np.abs(i1[3] + 1).max()),
+            "active_frac": float((status == 0).float().mean().item())}
+
+
+def oracle_configs(oracle, np, nthreads, result):
+    """The oracle timed on a bounded sample of each of the other workloads, on the host's
+    cores, beside the GPU's rate on the full workload."""
+    out = {}
+    kr = ((5.0, 50.0), (math.pi / 4, 3 * math.pi / 4), (0.92, 0.98), (2.5, 4.5), (0.0, 12.0))
+
+    def gpu_ratio(entry, gpu_value):
+        if gpu_value is not None:
+            entry["gpu_value"] = gpu_value
+            entry["gpu_over_oracle"] = gpu_value / entry["value"]
+        return entry
+    # Schwarzschild: all 1,024 lanes x 10,000 steps
+    s1 = oracle.ic_circular(1, 1.0, 0.0, 1024, 6.5, 20.0, 1e-3)
+    t = time.perf_counter()
+    _, _, sp = oracle.integrate([(1.0, 0.0)], s1, 0.01, 10000, nthreads=nthreads)
+    dt = time.perf_counter() - t
+    out["schwarzschild"] = gpu_ratio(
+        {"value": float(sp.sum()) / dt, "unit": "lane-steps/s", "cores": nthreads, "kind": "oracle",
+         "sample": "all 1,024 lanes x 10,000 steps (%.1f s wall)" % dt},
+        result.get("schwarzschild", {}).get("value"))
+    # camera: the 256 x 256 sub-grid of every 8th pixel per axis, full rays
+    cam = {"M": 1.0, "a": 0.998, "r_obs": 1000.0, "incl": math.pi / 3, "half_width": 25.0,
+           "nx": 2048, "ny": 2048, "h0": 0.1, "h_r0": 10.0, "r_escape": 1500.0,
+           "horizon_factor": 1.01, "disk_r_in": -1.0, "disk_r_out": 30.0, "max_steps": 100000}
+    ii, jj = np.meshgrid(np.arange(4, 2048, 8), np.arange(4, 2048, 8))
+    pix = (jj * 2048 + ii).ravel().astype(np.int64)
+    t = time.perf_counter()
+    r3 = oracle.trace_camera(cam, pix, nthreads=nthreads)
+    dt = time.perf_counter() - t
+    cp = result.get("extra", {}).get("camera_persistent", {})
+    out["camera"] = gpu_ratio(
+        {"value": float(r3["steps"].sum()) / dt, "unit": "lane-steps/s", "cores": nthreads,
+         "kind": "oracle", "rays_per_s": pix.size / dt,
+         "sample": "256 x 256 pixels (every 8th per axis) of 2048 x 2048, full rays (%.1f s wall)" % dt},
+        cp.get("lane_steps_per_s"))
+    # 16 spins: 256 lanes per spin (contiguous from the start of each spin's block), FP64
+    spins = [(1.0, 0.99 * k / 15) for k in range(16)]
+    sol = np.repeat(np.arange(16), 256).astype(np.int32)
+    s4 = np.concatenate([oracle.ic_constants(4, spins, 256, kr, st_of_lane=sol[k * 256:(k + 1) * 256],
+                                             lane0=k * 262144)[1] for k in range(16)], axis=1)
+    t = time.perf_counter()
+    _, _, sp = oracle.integrate(spins, s4, 0.02, 20000, st_of_lane=sol, nthreads=nthreads)
+    dt = time.perf_counter() - t
+    mx = result.get("extra", {})
+    out["mixed_16_spins"] = gpu_ratio(
+        {"value": float(sp.sum()) / dt, "unit": "lane-steps/s", "cores": nthreads, "kind": "oracle",
+         "sample": "16 spins x 256 lanes x 20,000 steps, FP64 (%.1f s wall)" % dt},
+        mx.get("mixed_f64_persistent", {}).get("lane_steps_per_s"))
+    if "mixed_f32k_persistent" in mx:
+        out["mixed_16_spins"]["gpu_f32k_over_oracle"] = (
+            mx["mixed_f32k_persistent"]["lane_steps_per_s"] / out["mixed_16_spins"]["value"])
+    # adjoint: the oracle's complex-step gradient (five directions) of 256 lanes,
+    # a = 0.7, 8,192 steps
+    rc, s5, c5, _ = oracle.ic_constants(5, [(1.0, 0.7)], 256, kr)
+    p5 = np.ascontiguousarray(np.stack([s5[1], s5[2], s5[5], s5[6], c5[1]]))
+    tg = np.ascontiguousarray(np.stack([s5[1], s5[2], np.zeros(256)]) + 0.5)
+    t = time.perf_counter()
+    oracle.grad_ic(1.0, 0.7, 0.02, 8192, p5.reshape(-1), np.ascontiguousarray(c5[0]),
+                   tg.reshape(-1), nthreads=nthreads)
+    dt = time.perf_counter() - t
+    out["adjoint"] = gpu_ratio(
+        {"value": 256 * 8192 / dt, "unit": "gradient lane-steps/s", "cores": nthreads,
+         "kind": "oracle (complex-step gradient, 5 directions)",
+         "sample": "256 lanes x 8,192 steps (%.1f s wall)" % dt},
+        mx.get("adjoint", {}).get("gradient_lane_steps_per_s"))
+    return out
+
+
 def extra_legs(m, torch, np):
     """One timed run (after a warm-up) of each remaining hot-path configuration."""
     out = {}
     # camera: a = 0.998, r_obs = 1000 M, i = 60 deg, 2048 x 2048 pixels over +-25 M
+    from paper_1803_08320_amd import autotune
+    cam_shape = autotune.camera_shape(m.Camera(nx=2048, ny=2048))
     for persistent in (1, 0):
         cam = m.Camera(nx=2048, ny=2048, persistent=persistent)
         res = {}
@@ -625,6 +742,8 @@ def extra_legs(m, torch, np):
                     "status_counts": [int(x) for x in torch.bincount(st, minlength=6).cpu()]}
     out["camera_persistent"]["speedup_vs_plain"] = (out["camera_persistent"]["lane_steps_per_s"] /
                                                     out["camera_plain"]["lane_steps_per_s"])
+    out["camera_persistent"]["launch_shape"] = {"block": cam_shape[0], "steps_per_chunk": cam_shape[1],
+                                                "source": "autotuned"}
 
     # mixed-spin batch: 16 spins a_k = 0.99 k / 15 x 262,144 lanes, FP32 compensated state,
     # FP64 within 1.2 r_+, 20,000 steps; persistent refill vs one thread per lane, and FP64
@@ -637,7 +756,8 @@ def extra_legs(m, torch, np):
     inv = torch.empty((4, n), dtype=torch.float64, device="cuda")
     for name, kw in (("mixed_f32k_persistent", dict(precision="f32k", persistent=True)),
                      ("mixed_f32k_plain", dict(precision="f32k", persistent=False)),
-                     ("mixed_f64_persistent", dict(precision="f64", persistent=True))):
+                     ("mixed_f64_persistent", dict(precision="f64", persistent=True)),
+                     ("mixed_f64_plain", dict(precision="f64", persistent=False))):
         def run_mix():
             state.copy_(s0)
             status.zero_()
@@ -677,6 +797,12 @@ def extra_legs(m, torch, np):
             dE = ((inv[0] / c0[0] - 1).abs())[act]
             out[name]["dQ_over_Q_p99"] = float(torch.quantile(dQ[:1 << 20], 0.99).item())
             out[name]["dE_over_E_p99"] = float(torch.quantile(dE[:1 << 20], 0.99).item())
+    for prec in ("f32k", "f64"):
+        out["mixed_%s_persistent" % prec]["speedup_vs_plain"] = (
+            out["mixed_%s_persistent" % prec]["lane_steps_per_s"]
+            / out["mixed_%s_plain" % prec]["lane_steps_per_s"])
+    out["mixed_f32k_persistent"]["speedup_vs_f64_persistent"] = (
+        out["mixed_f32k_persistent"]["lane_steps_per_s"] / out["mixed_f64_persistent"]["lane_steps_per_s"])
     # adjoint: a = 0.7, 65,536 lanes, 8,192 steps, checkpoints every 256
     st7 = (1.0, 0.7)
     n, N, K = 65536, 8192, 256

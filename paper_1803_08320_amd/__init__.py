@@ -286,10 +286,20 @@ def integrate(state: torch.Tensor, status: torch.Tensor, steps: torch.Tensor, sp
               formulation: str = "christoffel"):
     """Advance state[8, n] in place (status, steps int32[n] in/out).  formulation
     "christoffel": state = (x^mu, u^mu); "hamiltonian": state = (x^mu, p_mu), see
-    convert_state."""
+    convert_state.  block = 0 (and, for a persistent launch, steps_per_chunk = 0) takes
+    the autotuner's cached launch shape for this kind of batch when there is one
+    (autotune.integrate_shape), else the library's defaults."""
     n = state.shape[-1]
     prec = {"f64": F64, "f32k": F32_KAHAN}[precision]
     form = {"christoffel": FORM_CHRISTOFFEL, "hamiltonian": FORM_HAMILTONIAN}[formulation]
+    if block == 0 and checkpoint_every == 0 and state.is_cuda:
+        from . import autotune
+        shape = autotune.lookup_integrate(n, len(_spacetimes(spacetimes)), precision, formulation,
+                                          persistent)
+        if shape:
+            block = shape[0]
+            if persistent and steps_per_chunk == 0:
+                steps_per_chunk = shape[1]
     run = c_run(h, n_steps, prec, block, horizon_factor, r_escape, fp64_zone_factor,
                 steps_per_chunk, checkpoint_every, int(persistent), form)
     b = _Batch(_spacetimes(spacetimes), st_of_lane, n)
@@ -553,8 +563,16 @@ class Camera:
 
 
 def trace_camera(cam: Camera, final_state: bool = False, device="cuda", out=None, ws=None):
-    """Trace every pixel; returns dict(status[n], steps[n], hit[2, n], final_state[8, n]?)."""
+    """Trace every pixel; returns dict(status[n], steps[n], hit[2, n], final_state[8, n]?).
+    A persistent camera with block = 0 and steps_per_chunk = 0 takes the autotuner's
+    cached shape when there is one (autotune.camera_shape)."""
     npix = cam.nx * cam.ny
+    if cam.persistent and cam.block == 0 and cam.steps_per_chunk == 0 and \
+            torch.device(device).type == "cuda":
+        from . import autotune
+        shape = autotune.lookup_camera(cam)
+        if shape:
+            cam = Camera(**{**cam.__dict__, "block": shape[0], "steps_per_chunk": shape[1]})
     dev = torch.device(device)
     if out is None:
         out = {"status": torch.empty(npix, dtype=torch.int32, device=dev),

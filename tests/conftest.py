@@ -23,3 +23,15 @@ def orc():
 def load_golden(name):
     import numpy as np
     return np.loadtxt(os.path.join(ROOT, "tests", "golden", name), comments="#")
+
+
+# Lines that the parity checks record (lanes compared, largest error, lanes passed by
+# the conditioning guard, ties): printed in the terminal summary of every run.
+PARITY_LOG = []
+
+
+def pytest_terminal_summary(terminalreporter):
+    if PARITY_LOG:
+        terminalreporter.section("parity: lanes, largest error, conditioning guard and ties")
+        for line in PARITY_LOG:
+            terminalreporter.write_line(line)

@@ -5,16 +5,24 @@ must be <= TOL_F64 = 1e-10, and status and step count must match exactly.
 
 Conditioning guard: the GPU evaluates the same RK4 map with a different rounding
 order, so for an ill-conditioned lane (near-separatrix orbit, a near-tie at a
-termination threshold) the difference can exceed what rounding of a well-posed
-lane gives.  For every lane that fails the plain rule the oracle is re-run from
-initial data perturbed by one ulp in r; S = err(oracle, perturbed oracle).  The
-lane passes if its status and steps match the oracle's or the perturbed
-oracle's (a tie), and err <= max(TOL, 10 S).  Such lanes are counted and must
-stay rare.
+termination threshold, a lane that ends next to r_+) the difference can exceed what
+rounding of a well-posed lane gives.  For every lane that fails the plain rule the
+oracle is re-run from initial data with r moved up by k ulp, k = 1, 4, 16, 64, and
+S = the largest err(oracle, perturbed oracle).  (The GPU's rounding differs from the
+oracle's at every step, while a one-ulp change of the start alone is sometimes absorbed
+by rounding, S = 0; the spread over perturbations of up to 64 ulp is the oracle's own
+sensitivity.)  A lane with the oracle's status and step count passes ("guarded") if
+err <= 10 S; a lane whose status or step count differs passes only as a "tie": a
+perturbed oracle ends it exactly as the GPU did, and the GPU state is within
+max(TOL, 10 S) of that perturbed oracle's.  Guarded lanes and ties are counted, must
+stay rare, and are reported in the terminal summary of the test run.
 """
+import os
+
 import numpy as np
 
 TOL_F64 = 1e-10
+GUARD_ULPS = (1, 4, 16, 64)
 
 
 def mixed_rel(a, b):
@@ -25,34 +33,47 @@ def mixed_rel(a, b):
     return e.max(axis=0)
 
 
+def _record(stats, label):
+    try:
+        from conftest import PARITY_LOG
+    except ImportError:  # pragma: no cover
+        return
+    name = label or os.environ.get("PYTEST_CURRENT_TEST", "?").split(" ")[0]
+    PARITY_LOG.append("%s: %d lanes, largest error %.2e, guarded %d, ties %d" % (
+        name, stats["n"], stats["max_err"], stats["guarded"], stats["ties"]))
+
+
 def compare(orc, spacetimes, s0, got_state, got_status, got_steps, ref_state, ref_status,
-            ref_steps, rerun, tol=TOL_F64, max_guarded_frac=0.01):
+            ref_steps, rerun, tol=TOL_F64, max_guarded_frac=0.01, label=None):
     """rerun(state0) -> (state, status, steps) from the oracle; returns stats dict."""
     err = mixed_rel(got_state, ref_state)
     bad = (err > tol) | (got_status != ref_status) | (got_steps != ref_steps)
     idx = np.flatnonzero(bad)
-    guarded = 0
+    guarded = ties = 0
     failures = []
     if idx.size:
+        runs = []
         p0 = s0[:, idx].copy()
-        p0[1] = np.nextafter(p0[1], np.inf)
-        ps, pst, psp = rerun(p0)
-        S = mixed_rel(ps, ref_state[:, idx])
+        for k in range(1, GUARD_ULPS[-1] + 1):
+            p0[1] = np.nextafter(p0[1], np.inf)
+            if k in GUARD_ULPS:
+                runs.append(rerun(p0.copy()))
+        S = np.max([mixed_rel(ps, ref_state[:, idx]) for ps, _, _ in runs], axis=0)
         for j, i in enumerate(idx):
-            tie = (got_status[i] == ref_status[i] and got_steps[i] == ref_steps[i]) or (
-                got_status[i] == pst[j] and got_steps[i] == psp[j])
-            if got_status[i] == pst[j] and got_steps[i] == psp[j]:
-                e = mixed_rel(got_state[:, i:i + 1], ps[:, j:j + 1])[0]
-                e = min(e, err[i])
-            else:
-                e = err[i]
-            if tie and e <= max(tol, 10.0 * S[j]):
+            same = got_status[i] == ref_status[i] and got_steps[i] == ref_steps[i]
+            e_pert = min([mixed_rel(got_state[:, i:i + 1], ps[:, j:j + 1])[0]
+                          for ps, pst, psp in runs
+                          if got_status[i] == pst[j] and got_steps[i] == psp[j]], default=np.inf)
+            if same and min(err[i], e_pert) <= max(tol, 10.0 * S[j]):
                 guarded += 1
+            elif not same and e_pert <= max(tol, 10.0 * S[j]):
+                ties += 1
             else:
                 failures.append((int(i), float(err[i]), int(got_status[i]), int(ref_status[i]),
                                  int(got_steps[i]), int(ref_steps[i]), float(S[j])))
     stats = {"n": err.size, "max_err": float(np.max(err[~bad])) if (~bad).any() else 0.0,
-             "guarded": guarded, "failures": failures}
+             "guarded": guarded, "ties": ties, "failures": failures}
+    _record(stats, label)
     assert not failures, "parity failures (lane, err, st, st_ref, steps, steps_ref, S): %s" % failures[:10]
-    assert guarded <= max(2, max_guarded_frac * err.size), stats
+    assert guarded + ties <= max(2, max_guarded_frac * err.size), stats
     return stats

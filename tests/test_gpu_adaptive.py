@@ -5,7 +5,7 @@ import math
 import numpy as np
 import pytest
 
-from parity import compare
+from parity import TOL_F64, compare, mixed_rel
 
 pytestmark = pytest.mark.gpu
 
@@ -68,8 +68,21 @@ def check(orc, sts, s0, got, ref, tau_end, h0, **kw):
         return y, st, key(sp, rj)
     both_hz = (got[3] == 1) & (ref[3] == 1)
     g0 = np.where(both_hz[None, :], ref[0], got[0])
-    stats = compare(orc, sts, s0, g0, got[3], key(got[4], got[5]), ref[0], ref[3],
-                    key(ref[4], ref[5]), rerun)
+    # end-of-interval splits: both sides active on tau_end with the same state (1e-10),
+    # the same rejections and one accepted attempt more on one side.  The last attempt is
+    # clipped to land on tau_end, and the two sides' step sizes differ by ~1e-5 relative
+    # (err^(-1/5) of a cancelling difference), so the penultimate step can stop just
+    # short of tau_end on one side (which then takes a sliver of a step) and reach it on
+    # the other; such lanes are counted as ties.
+    split = ((got[3] == 0) & (ref[3] == 0) & (got[1] == tau_end) & (ref[1] == tau_end)
+             & (got[5] == ref[5]) & (np.abs(got[4].astype(np.int64) - ref[4]) == 1)
+             & (mixed_rel(got[0], ref[0]) <= TOL_F64))
+    gkey = np.where(split, key(ref[4], ref[5]), key(got[4], got[5]))
+    stats = compare(orc, sts, s0, g0, got[3], gkey, ref[0], ref[3], key(ref[4], ref[5]), rerun)
+    from conftest import PARITY_LOG
+    PARITY_LOG.append("    (of them %d end-of-interval splits: one accepted attempt more on one side)"
+                      % int(split.sum()))
+    assert split.sum() <= max(2, 0.001 * split.size)
     same = (got[3] == ref[3]) & (got[4] == ref[4]) & (got[5] == ref[5])
     # the affine parameter lands exactly on tau_end for lanes still active
     act = same & (ref[3] == 0)
@@ -132,18 +145,17 @@ def test_persistent_equals_plain_bitwise_and_budget(m, orc):
 
 def test_adaptive_full_size_sampled(m, orc):
     """The benchmark's adaptive launch: Kerr a = 0.9, 1,048,576 lanes to tau = 400 at
-    rtol = atol = 1e-12 under the persistent queue in periapsis order.  256 strided lanes hold the
+    rtol = atol = 1e-12 under the persistent queue in periapsis order.  8,192 strided lanes hold the
     oracle's own initial data (the device builder's agree with it to the rounding of
     sqrt(R)) and are compared with the oracle; over all lanes, active ones end on
     tau_end."""
     import torch
-    from parity import mixed_rel
     st = [(1.0, 0.9)]
     n = 1 << 20
     spec = m.ICSpec(mode=m.IC_CONSTANTS, seed=2, r_range=KERR_RANGES[0], th_range=KERR_RANGES[1],
                     E_range=KERR_RANGES[2], Lz_range=KERR_RANGES[3], Q_range=KERR_RANGES[4])
     state, consts, _ = m.init_particles(spec, st, n)
-    idx = np.arange(0, n, n // 256)
+    idx = np.arange(0, n, n // 8192)
     s0 = np.concatenate([orc.ic_constants(2, st, 1, KERR_RANGES, lane0=int(i))[1] for i in idx], axis=1)
     assert mixed_rel(state.cpu().numpy()[:, idx], s0).max() < 5e-13
     state[:, torch.as_tensor(idx, device="cuda")] = to_dev(s0, torch.float64)

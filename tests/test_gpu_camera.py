@@ -1,6 +1,7 @@
 """GPU parity of the camera (backward null rays with a thin disk) against the oracle,
 and bitwise agreement of the persistent work-queue kernel with the
-one-thread-per-pixel kernel."""
+one-thread-per-pixel kernel.  Every ray's final state is compared, those that end at
+the horizon or unresolved included, under the conditioning guard below."""
 import math
 
 import numpy as np
@@ -10,17 +11,27 @@ pytestmark = pytest.mark.gpu
 
 # r_c and phi_c are linear interpolations between two states that each match to
 # 1e-10; the interpolation weight divides by cos(theta_n) - cos(theta_{n+1}), which
-# is small for grazing crossings, so the hit point is held to 1e-9.  A ray that
-# ends at the horizon stores a state next to the coordinate singularity at r_+
-# (its last step is evaluated where Delta -> 0), and a NONFINITE ray the state
-# just before a step that the coordinates could not resolve, so for HORIZON and
-# NONFINITE rays only the status and the step count are compared.
+# is small for grazing crossings, so the hit point is held to 1e-9.
 TOL_STATE = 1e-10
 TOL_HIT = 1e-9
 # Rays with |alpha| below this pass next to a pole, where a fixed Boyer-Lindquist
 # step cannot resolve the 1/sin^2 theta terms: they may end NONFINITE (rule: theta
 # left (0, pi)) or be classified by a garbage step.
 NEAR_AXIS = 0.5
+# Conditioning guard of a ray: the oracle re-traced with r_obs moved up by k ulp,
+# k = 1, 4, 16, 64; S = the largest change of its result.  The GPU's rounding differs
+# from the oracle's at every one of the ray's ~500 steps, while a one-ulp change of
+# the start is often absorbed by the first step's rounding (S = 0 for about a third of
+# the rays that need the guard), so the spread over perturbations up to 64 ulp is the
+# oracle's own sensitivity the comparison allows 10x of.
+GUARD_ULPS = (1, 4, 16, 64)
+# Rays that end next to a coordinate singularity (HORIZON: r_+, where u^t ~ 1/Delta;
+# NONFINITE: the step before the one the coordinates could not resolve) amplify the
+# rounding differences of their last steps: 1.4 % of NONFINITE and 0.7 % of HORIZON
+# rays need the guard (measured on 4,096 of each at 2048 x 2048), against none of the
+# escaping and disk rays.
+MAX_GUARDED_REGULAR = 0.005
+MAX_GUARDED_SINGULAR = 0.03
 
 
 @pytest.fixture(scope="module")
@@ -53,55 +64,69 @@ def rel(a, b):
     return np.where(np.isnan(a) & np.isnan(b), 0.0, np.where(np.isnan(e), np.inf, e))
 
 
-def check_against_oracle(orc, cam, got, pix):
+def check_against_oracle(orc, cam, got, pix, label):
     ref = orc.trace_camera(cam_dict(cam, orc), pix, final_state=True)
     st_ok = (got["status"][pix] == ref["status"]) & (got["steps"][pix] == ref["steps"])
     e_state = rel(got["final_state"][:, pix], ref["final_state"]).max(axis=0)
-    # HORIZON and NONFINITE rays end next to a coordinate singularity (r_+, or the
-    # axis), where the last accepted state amplifies rounding without bound: for
-    # them the status and the step count are the comparison
-    e_state[(ref["status"] == 1) & (got["status"][pix] == 1)] = 0.0
-    e_state[(ref["status"] == 4) & (got["status"][pix] == 4)] = 0.0
     e_hit = rel(got["hit"][:, pix], ref["hit"]).max(axis=0)
     bad = np.flatnonzero(~st_ok | (e_state > TOL_STATE) | (e_hit > TOL_HIT))
-    guarded = 0
+    w = cam.half_width
+    r_in = cam.disk_r_in if cam.disk_r_in > 0 else orc.r_isco(cam.M, cam.a, True)
+    guarded = ties = 0
+    singular = np.isin(ref["status"], (1, 4))
+    n_sing = guarded_sing = 0
     for q in bad:
-        # conditioning guard: re-trace the ray with alpha moved by 64 ulp (about the
-        # size of the rounding differences a few hundred steps accumulate); a lane
-        # whose oracle outcome changes under that is a near-tie, not a failure
         p = pix[q]
         i, j = p % cam.nx, p // cam.nx
-        w = cam.half_width
         al = -w + (i + 0.5) * 2 * w / cam.nx
         be = -w + (j + 0.5) * 2 * w / cam.ny
-        r_in = cam.disk_r_in if cam.disk_r_in > 0 else orc.r_isco(cam.M, cam.a, True)
-        al_p = al + 64 * np.spacing(al)
-        sp, stp, hp, fp = orc.trace_rays(cam.M, cam.a, cam.r_obs, cam.incl, [al_p],
-                                         [be], cam.h0, cam.h_r0, cam.r_escape, cam.horizon_factor,
-                                         r_in, cam.disk_r_out, cam.max_steps, final_state=True)
-        S_state = rel(fp[:, 0], ref["final_state"][:, q]).max() if ref["status"][q] not in (1, 4) else 0.0
-        S_hit = rel(hp[:, 0], ref["hit"][:, q]).max()
-        same_outcome = sp[0] == ref["status"][q] and stp[0] == ref["steps"][q]
-        tie = (got["status"][p], got["steps"][p]) in ((ref["status"][q], ref["steps"][q]), (sp[0], stp[0]))
-        if same_outcome and got["status"][p] == ref["status"][q] and got["steps"][p] == ref["steps"][q]:
-            # same outcome: the state and hit point must agree to 10x the oracle's own
-            # sensitivity to a 1-ulp change of the ray
+        runs = []
+        robs = cam.r_obs
+        for k in range(1, GUARD_ULPS[-1] + 1):
+            robs = np.nextafter(robs, np.inf)
+            if k in GUARD_ULPS:
+                runs.append(orc.trace_rays(cam.M, cam.a, robs, cam.incl, [al], [be], cam.h0,
+                                           cam.h_r0, cam.r_escape, cam.horizon_factor, r_in,
+                                           cam.disk_r_out, cam.max_steps, final_state=True))
+        same_ref = lambda sp, stp: sp[0] == ref["status"][q] and stp[0] == ref["steps"][q]
+        S_state = max(rel(fp[:, 0], ref["final_state"][:, q]).max() for sp, stp, hp, fp in runs)
+        S_hit = max(rel(hp[:, 0], ref["hit"][:, q]).max() for sp, stp, hp, fp in runs)
+        got_out = (got["status"][p], got["steps"][p])
+        if got_out == (ref["status"][q], ref["steps"][q]):
             ok = e_state[q] <= max(TOL_STATE, 10 * S_state) and e_hit[q] <= max(TOL_HIT, 10 * S_hit)
+            guarded += ok
         else:
-            ok = tie and not same_outcome
+            # a tie: a perturbed oracle ends the ray as the GPU did, with the GPU's state
+            # and hit point within 10x the spread of the perturbed results
+            ok = False
+            for sp, stp, hp, fp in runs:
+                if (sp[0], stp[0]) == got_out and not same_ref(sp, stp):
+                    ok = ok or (rel(got["final_state"][:, p], fp[:, 0]).max() <= max(TOL_STATE, 10 * S_state)
+                                and rel(got["hit"][:, p], hp[:, 0]).max() <= max(TOL_HIT, 10 * S_hit))
+            ties += ok
         assert ok, ("camera parity failure", int(p), int(got["status"][p]), int(ref["status"][q]),
                     int(got["steps"][p]), int(ref["steps"][q]), float(e_state[q]), float(e_hit[q]),
                     float(S_state), float(S_hit))
-        guarded += 1
-    assert guarded <= max(2, 0.005 * pix.size), guarded
-    return ref, guarded
+        guarded_sing += bool(singular[q])
+    n_sing = int(singular.sum())
+    n_reg = pix.size - n_sing
+    g_reg = guarded + ties - guarded_sing
+    from conftest import PARITY_LOG
+    PARITY_LOG.append("%s: %d rays (%d ending at a singularity), largest error %.2e (state) %.2e "
+                      "(hit), guarded %d, ties %d (%d of them ending at a singularity)" % (
+                          label, pix.size, n_sing, float(np.max(e_state[~np.isin(np.arange(pix.size), bad)], initial=0.0)),
+                          float(np.max(e_hit[~np.isin(np.arange(pix.size), bad)], initial=0.0)),
+                          guarded, ties, guarded_sing))
+    assert g_reg <= max(2, MAX_GUARDED_REGULAR * n_reg), (g_reg, n_reg)
+    assert guarded_sing <= max(2, MAX_GUARDED_SINGULAR * n_sing), (guarded_sing, n_sing)
+    return ref, guarded + ties
 
 
 def test_small_camera_full_parity(m, orc):
     cam = m.Camera(nx=64, ny=64)
     got = gpu_trace(m, cam)
     pix = np.arange(64 * 64)
-    ref, guarded = check_against_oracle(orc, cam, got, pix)
+    ref, guarded = check_against_oracle(orc, cam, got, pix, "camera 64 x 64, every pixel")
     counts = np.bincount(got["status"], minlength=6)
     assert counts[3] > 500 and counts[2] > 500 and counts[1] > 0, counts
     assert counts[5] == 0
@@ -121,18 +146,21 @@ def test_persistent_equals_plain_bitwise(m, nx, ny, chunk):
 
 
 def test_full_size_camera_sampled(m, orc):
-    """2048 x 2048 pixels, persistent kernel, compared on 1,024 strided pixels."""
+    """2048 x 2048 pixels, persistent kernel (the benchmark's launch): every 16th pixel
+    per axis (16,384), and 4,096 each of the rays that end NONFINITE and HORIZON, against
+    the oracle."""
     cam = m.Camera(nx=2048, ny=2048)
     got = gpu_trace(m, cam)
-    pix = np.arange(0, 2048 * 2048, 4096 + 37)[:1024].astype(np.int64)
-    check_against_oracle(orc, cam, got, pix)
+    ii, jj = np.meshgrid(np.arange(7, 2048, 16), np.arange(9, 2048, 16))
+    pix = (jj * 2048 + ii).ravel().astype(np.int64)
+    check_against_oracle(orc, cam, got, pix, "camera 2048 x 2048, 128 x 128 pixel grid")
     st = got["status"]
     assert set(np.unique(st)) <= {1, 2, 3, 4}
     # unresolved (NONFINITE) rays: those that pass next to a pole, where the closest
     # approach to the axis, sin(theta_min) ~ |L_z| / sqrt(Q + L_z^2), is small, and
     # plunging rays whose last step, taken just outside the stop radius with the
     # fixed near-hole step h0, throws theta out of (0, pi); the final state is the
-    # last accepted one.  A spread of them is also checked against the oracle.
+    # last accepted one.
     p_all = np.arange(2048 * 2048)
     alpha = -25.0 + (p_all % 2048 + 0.5) * 50.0 / 2048
     beta = -25.0 + (p_all // 2048 + 0.5) * 50.0 / 2048
@@ -145,11 +173,17 @@ def test_full_size_camera_sampled(m, orc):
     off = nf[(smin[nf] >= 0.05) & (r_last[nf] >= 1.5 * r_plus)]
     assert off.size == 0, [(float(alpha[p]), float(beta[p]), float(smin[p]), float(r_last[p]),
                             int(got["steps"][p])) for p in off[:10]]
-    print("NONFINITE fraction %.2e (near axis %d, near horizon %d)" % (
-        nf.size / st.size, int((smin[nf] < 0.05).sum()), int((smin[nf] >= 0.05).sum())))
-    if nf.size:
-        check_against_oracle(orc, cam, got, nf[np.linspace(0, nf.size - 1, 32).astype(np.int64)])
-    assert (st == 4).mean() < 4e-3  # 2.3e-3 measured
+    from conftest import PARITY_LOG
+    PARITY_LOG.append("camera 2048 x 2048: NONFINITE fraction %.3e (near the axis %d, near the "
+                      "horizon %d), HORIZON fraction %.3e" % (
+                          nf.size / st.size, int((smin[nf] < 0.05).sum()),
+                          int((smin[nf] >= 0.05).sum()), (st == 1).mean()))
+    hz = np.flatnonzero(st == 1)
+    for sel, name in ((nf, "NONFINITE"), (hz, "HORIZON")):
+        check_against_oracle(orc, cam, got, sel[np.linspace(0, sel.size - 1, min(sel.size, 4096)).astype(np.int64)],
+                             "camera 2048 x 2048, rays ending %s" % name)
+    # the unresolved fraction (2.31e-3 measured; both sides agree on those rays)
+    assert 2.2e-3 < (st == 4).mean() < 2.42e-3
     assert got["steps"].max() < cam.max_steps
 
 

@@ -1,8 +1,11 @@
 """FP32 compensated integrator (FP64 near the horizon) against the FP64 oracle.
 
 The paper fixes no FP32 accuracy (parity unpinned by the paper); the bounds
-asserted here are the measured error of this path against the FP64 oracle,
-with margin: they are the stated accuracy of the FP32-compensated result.
+asserted here are the stated accuracy of the FP32-compensated result after 20,000
+steps of h = 0.02, set at about 10x the measured p99 values (measured on the
+1M-lane Kerr a = 0.9 batch: |dE/E| 1.0e-8, |dQ/Q| 1.8e-7, position 7.3e-6; on the
+reduced 16-spin test 8.4e-9, 1.6e-7 and 6.6e-6; on 4,096 lanes of the full 16-spin
+batch 1.0e-8, 1.6e-7 and 8.2e-6).
 """
 import math
 
@@ -15,6 +18,8 @@ pytestmark = pytest.mark.gpu
 
 KERR_RANGES = ((5.0, 50.0), (math.pi / 4, 3 * math.pi / 4), (0.92, 0.98), (2.5, 4.5), (0.0, 12.0))
 SPINS = [(1.0, 0.99 * k / 15) for k in range(16)]
+# stated p99 accuracy of the FP32-compensated state against the FP64 oracle
+F32K_DE_P99, F32K_DQ_P99, F32K_POS_P99 = 1e-7, 2e-6, 1e-4
 
 
 @pytest.fixture(scope="module")
@@ -84,9 +89,9 @@ def test_mixed_batch_accuracy(m, orc):
     stats = dict(dE_p99=np.quantile(dE, 0.99), dQ_p99=np.quantile(dQ, 0.99),
                  pos_p50=np.quantile(pos, 0.5), pos_p99=np.quantile(pos, 0.99), pos_max=pos.max())
     print("f32k accuracy vs fp64 oracle:", {k: "%.2e" % v for k, v in stats.items()})
-    assert stats["dE_p99"] < 1e-5
-    assert stats["dQ_p99"] < 1e-4
-    assert stats["pos_p99"] < 1e-2
+    assert stats["dE_p99"] < F32K_DE_P99
+    assert stats["dQ_p99"] < F32K_DQ_P99
+    assert stats["pos_p99"] < F32K_POS_P99
 
 
 def test_mixed_statuses_and_inactive_lanes(m, orc):
@@ -189,8 +194,10 @@ def test_hamiltonian_mixed_batch_accuracy(m, orc):
     pos = position_error(a_lane[both], got[0][:, both], ref[0][:, both])
     stats = dict(dQ_p99=np.quantile(dQ, 0.99), pos_p99=np.quantile(pos, 0.99))
     print("f32k Hamiltonian accuracy vs fp64 oracle:", {k: "%.2e" % v for k, v in stats.items()})
-    assert stats["dQ_p99"] < 1e-4
-    assert stats["pos_p99"] < 1e-2
+    # measured: p99 |dQ/Q| 1.1e-7, position 4.7e-5 (the momenta's FP32 rounding moves
+    # the orbital phase more than the velocities' does in the Christoffel form)
+    assert stats["dQ_p99"] < 1e-6
+    assert stats["pos_p99"] < 5e-4
 
 
 @pytest.mark.parametrize("chunk", [1, 64])
@@ -221,7 +228,7 @@ def test_hamiltonian_f32k_persistent_equals_plain(m, orc, chunk):
 
 def test_mixed_full_size_sampled(m, orc):
     """The benchmark's mixed-spin launches: 16 spins x 262,144 contiguous lanes
-    (4,194,304), 20,000 steps, persistent queue.  16 strided lanes per spin hold the
+    (4,194,304), 20,000 steps, persistent queue.  256 strided lanes per spin hold the
     oracle's initial data.  FP64: parity with the oracle on those lanes.  FP32
     compensated: the accuracy bounds of the reduced test, on the same lanes."""
     import torch
@@ -230,7 +237,7 @@ def test_mixed_full_size_sampled(m, orc):
     sol_h = np.repeat(np.arange(16), per).astype(np.int32)
     sol = torch.as_tensor(sol_h).cuda()
     s_dev, c_dev, _ = m.init_particles(m.ICSpec(mode=m.IC_CONSTANTS, seed=4), SPINS, n, st_of_lane=sol)
-    idx = np.concatenate([k * per + np.arange(0, per, per // 16) for k in range(16)])
+    idx = np.concatenate([k * per + np.arange(0, per, per // 256) for k in range(16)])
     spin = sol_h[idx]
     s0 = np.concatenate([orc.ic_constants(4, SPINS, 1, KERR_RANGES, st_of_lane=spin[j:j + 1],
                                           lane0=int(i))[1] for j, i in enumerate(idx)], axis=1)
@@ -250,17 +257,24 @@ def test_mixed_full_size_sampled(m, orc):
         torch.cuda.synchronize()
         out[prec] = (state.cpu().numpy()[:, idx], status.cpu().numpy()[idx], steps.cpu().numpy()[idx])
     del state, s_dev
+    # per spin: low spins plunge in up to half of their lanes, and a plunging lane ends
+    # next to r_+ (ill-conditioned), so one spin's 256 lanes may need the guard a little
+    # more often than 1 %; over all 4,096 sampled lanes the 1 % cap holds
+    n_guard = 0
     for k in range(16):
         sel = spin == k
         got = tuple(x[..., sel] for x in out["f64"])
-        compare(orc, [SPINS[k]], s0[:, sel], *got, ref[0][:, sel], ref[1][sel], ref[2][sel],
-                lambda p0, k=k: orc.integrate([SPINS[k]], p0, 0.02, 20000))
+        st_k = compare(orc, [SPINS[k]], s0[:, sel], *got, ref[0][:, sel], ref[1][sel], ref[2][sel],
+                       lambda p0, k=k: orc.integrate([SPINS[k]], p0, 0.02, 20000),
+                       max_guarded_frac=0.03, label="mixed 16 spins, FP64, a = %.3f" % SPINS[k][1])
+        n_guard += st_k["guarded"] + st_k["ties"]
+    assert n_guard <= 0.01 * idx.size, n_guard
     got = out["f32k"]
     plunge = ref[1] == 1
     assert plunge.sum() > 10
     # a near-critical lane may stop a step earlier or later, or on the other side of
     # the horizon test, under the ~1e-7 relative FP32 rounding
-    assert np.sum((got[1] == 1) != plunge) <= 1
+    assert np.sum((got[1] == 1) != plunge) <= 4
     both_pl = plunge & (got[1] == 1)
     assert np.all(np.abs(got[2][both_pl] - ref[2][both_pl]) <= 3)
     both = (got[1] == 0) & (ref[1] == 0)
@@ -271,6 +285,6 @@ def test_mixed_full_size_sampled(m, orc):
     pos = position_error(a_lane[both], got[0][:, both], ref[0][:, both])
     print("f32k full size vs fp64 oracle: dE p99 %.2e dQ p99 %.2e pos p99 %.2e"
           % (np.quantile(dE, 0.99), np.quantile(dQ, 0.99), np.quantile(pos, 0.99)))
-    assert np.quantile(dE, 0.99) < 1e-5
-    assert np.quantile(dQ, 0.99) < 1e-4
-    assert np.quantile(pos, 0.99) < 1e-2
+    assert np.quantile(dE, 0.99) < F32K_DE_P99
+    assert np.quantile(dQ, 0.99) < F32K_DQ_P99
+    assert np.quantile(pos, 0.99) < F32K_POS_P99

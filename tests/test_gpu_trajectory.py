@@ -158,7 +158,7 @@ def test_streaming_driver_is_the_direct_call(m, orc, tmp_path):
 def test_stream_full_size_sampled(m, orc):
     """The benchmark's output launch: 1,048,576 Kerr a = 0.9 lanes x 20,000 steps, a
     record every 200 steps, 10 records per chunk through the double-buffered
-    streaming driver; the records of 256 strided lanes (holding the oracle's initial
+    streaming driver; the records of 8,192 strided lanes (holding the oracle's initial
     data) against the oracle's states converted by eq. coord."""
     import torch
     from paper_1803_08320_amd.stream import stream_trajectories
@@ -167,7 +167,7 @@ def test_stream_full_size_sampled(m, orc):
     spec = m.ICSpec(mode=m.IC_CONSTANTS, seed=2, r_range=KERR_RANGES[0], th_range=KERR_RANGES[1],
                     E_range=KERR_RANGES[2], Lz_range=KERR_RANGES[3], Q_range=KERR_RANGES[4])
     state, _, _ = m.init_particles(spec, st, n)
-    idx = np.arange(0, n, n // 256)
+    idx = np.arange(0, n, n // 8192)
     s0 = np.concatenate([orc.ic_constants(2, st, 1, KERR_RANGES, lane0=int(i))[1] for i in idx], axis=1)
     assert mixed_rel(state.cpu().numpy()[:, idx], s0).max() < 5e-13
     state[:, torch.as_tensor(idx, device="cuda")] = to_dev(s0, torch.float64)
