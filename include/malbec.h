@@ -221,7 +221,7 @@ MALBEC_API const char *malbec_last_error(void);
 MALBEC_API int malbec_version(void);
 
 /* Bytes of caller workspace an operation needs: op = MALBEC_OP_INTEGRATE (n lanes,
- * aux = run->persistent), MALBEC_OP_CAMERA (n = nx * ny pixels), MALBEC_OP_ADJOINT
+ * aux = run->persistent), MALBEC_OP_CAMERA (n = nx * ny pixels: 256 + 64n bytes), MALBEC_OP_ADJOINT
  * (n lanes, aux = the checkpoint interval K: K * 8 * n doubles),
  * MALBEC_OP_ADAPTIVE (n lanes, aux = ad->persistent ? 1 + ad->schedule : 0; about
  * 8n bytes with the periapsis schedule) or MALBEC_OP_ADAPTIVE_ORDER (n lanes, aux
@@ -309,7 +309,8 @@ MALBEC_API int malbec_integrate_record(const malbec_run *run, const malbec_batch
  * status, steps: device nx*ny int32 (out).  hit: device 2*nx*ny doubles (out),
  * component-major (r_c, phi_c), NaN unless DISK.  final_state: device 8*nx*ny
  * (out, nullable).  ws: caller workspace of malbec_workspace_bytes(MALBEC_OP_CAMERA,
- * nx*ny) bytes (the persistent kernel's work counter).
+ * nx*ny) bytes (the persistent kernel's work counter and the rays' initial states,
+ * 256 + 64 nx*ny bytes).
  * Errors: MALBEC_EINVAL, MALBEC_ENOMEM, MALBEC_EDEVICE. */
 MALBEC_API int malbec_trace_camera(const malbec_camera *cam, int32_t *status, int32_t *steps, double *hit,
                         double *final_state, void *ws, size_t ws_bytes, void *stream);

@@ -56,23 +56,25 @@ __device__ __forceinline__ double rpow5(double err)
 
 struct AdProg {
     const AdArgs &A;
-    const Spacetime *table;
+    const Spacetime *table;  // LDS copy of the spacetimes (mixed batch)
     bool multi;
     int32_t n_st;
+    Spacetime st0;           // the one spacetime of a single-spin batch (kernel argument)
     struct Lane {
         double y[8];
-        Deriv<double> k1;
-        Spacetime S;
-        double tau, h, facmax;
-        int64_t attempts;
-        int32_t st, acc, rej;
+        double k1a[4];  // acceleration at y (k1 = (y[4..7], k1a): its velocity part is y's)
+        int32_t sid;    // spacetime index (its parameters are read when needed)
+        double tau, h;
+        int32_t st, acc, rej;  // acc + rej = the attempts of this call so far
+        bool capped;           // the last attempt was rejected: no growth in the next
     };
+    __device__ __forceinline__ Spacetime space(const Lane &L) const { return multi ? table[L.sid] : st0; }
     __device__ __forceinline__ void deriv0(Lane &L)
     {
-        AccelF64 f{L.S.M, L.S.a, {}};
-        for (int c = 0; c < 4; ++c) L.k1.u[c] = L.y[4 + c];
-        f(0, L.y[1], L.y[2], L.y[4], L.y[5], L.y[6], L.y[7], L.k1.acc[0], L.k1.acc[1], L.k1.acc[2],
-          L.k1.acc[3]);
+        const Spacetime S = space(L);
+        AccelF64 f{S.M, S.a, {}};
+        f(0, L.y[1], L.y[2], L.y[4], L.y[5], L.y[6], L.y[7], L.k1a[0], L.k1a[1], L.k1a[2],
+          L.k1a[3]);
     }
     __device__ __forceinline__ int64_t lane_of(int64_t item) const
     {
@@ -91,14 +93,13 @@ struct AdProg {
                 return false;
             }
         }
-        L.S = table[sid];
+        L.sid = sid;
         L.tau = A.tau[i];
         if (!(L.tau < A.tau_end)) return false;
 #pragma unroll
         for (int k = 0; k < 8; ++k) L.y[k] = A.state[k * A.n + i];
         L.h = A.h[i];
-        L.facmax = A.facmax;
-        L.attempts = 0;
+        L.capped = false;
         L.acc = 0;
         L.rej = 0;
         deriv0(L);
@@ -107,11 +108,10 @@ struct AdProg {
     // one attempt; true when the lane is finished for this call
     __device__ __forceinline__ bool step(Lane &L)
     {
-        if (L.attempts == A.max_attempts) {
+        if ((int64_t)L.acc + L.rej == A.max_attempts) {
             L.st = kBudget;
             return true;
         }
-        ++L.attempts;
         double hh = L.h;
         bool last = false;
         if (L.tau + hh >= A.tau_end) {
@@ -119,15 +119,21 @@ struct AdProg {
             last = true;
         }
         // stage 0 of the rotation base is the start point: sin and cos evaluated fresh
-        AccelF64 f{L.S.M, L.S.a, {}};
+        const Spacetime S = space(L);
+        AccelF64 f{S.M, S.a, {}};
         {
             double s, c;
             f.trig(0, L.y[2], s, c);
         }
         double y1[8], e[8], sr[5];
-        Deriv<double> k7;
-        dp45_attempt(f, hh, L.y, L.k1, y1, e, k7, sr);
-        const double rs = L.S.r_stop;
+        Deriv<double> k1, k7;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            k1.u[c] = L.y[4 + c];
+            k1.acc[c] = L.k1a[c];
+        }
+        dp45_attempt(f, hh, L.y, k1, y1, e, k7, sr);
+        const double rs = S.r_stop;
         if (sr[0] <= rs || sr[1] <= rs || sr[2] <= rs || sr[3] <= rs || sr[4] <= rs) {
             L.st = kHorizon;
             return true;
@@ -148,17 +154,18 @@ struct AdProg {
         if (err <= 1.0) {
 #pragma unroll
             for (int c = 0; c < 8; ++c) L.y[c] = y1[c];
-            L.k1 = k7;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) L.k1a[c] = k7.acc[c];
             L.tau = last ? A.tau_end : L.tau + hh;
             ++L.acc;
-            L.h = hh * fmin(L.facmax, fmax(A.facmin, grow));
-            L.facmax = A.facmax;
+            L.h = hh * fmin(L.capped ? 1.0 : A.facmax, fmax(A.facmin, grow));
+            L.capped = false;
             if (L.y[1] <= rs) L.st = kHorizon;
             else if (L.y[1] >= A.r_escape) L.st = kEscape;
         } else {
             ++L.rej;
             L.h = hh * fmin(1.0, fmax(A.facmin, grow));
-            L.facmax = 1.0;
+            L.capped = true;
         }
         return L.st != kActive || !(L.tau < A.tau_end);
     }
@@ -185,7 +192,7 @@ __global__ void __launch_bounds__(256) dp45_kernel(AdArgs A, StTable T)
     __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= A.n) return;
-    AdProg P{A, lds_st, MULTI, T.n_st};
+    AdProg P{A, lds_st, MULTI, T.n_st, T.st[0]};
     AdProg::Lane L;
     if (!P.load(i, L)) return;
     while (!P.step(L)) {
@@ -201,7 +208,7 @@ __global__ void __launch_bounds__(256) dp45_persistent_kernel(AdArgs A, StTable 
     __shared__ Spacetime lds_st[kMaxSt];
     for (int k = threadIdx.x; k < T.n_st; k += blockDim.x) lds_st[k] = T.st[k];
     __syncthreads();
-    AdProg P{A, lds_st, MULTI, T.n_st};
+    AdProg P{A, lds_st, MULTI, T.n_st, T.st[0]};
     persistent_loop(P, A.n, counter, chunk);
 }
 

@@ -3,15 +3,16 @@
 // Forward: malbec_integrate with checkpoint_every = K stores the state every K steps.
 // Backward, per lane and per segment s = last .. 0: recompute the K step-start
 // states from checkpoint s into the workspace (coalesced [K][8][n] doubles), then
-// walk them in reverse applying the transposed RK4 step
+// walk them in reverse applying the transposed RK4 step (rk4_vjp):
 //     lam_y  = lam + J(Y4)^T lam_k4 + J(Y3)^T lam_k3 + J(Y2)^T lam_k2 + J(y)^T lam_k1,
 //     lam_k4 = h/6 lam, lam_k3 = h/3 lam + h J(Y4)^T lam_k4,
 //     lam_k2 = h/3 lam + h/2 J(Y3)^T lam_k3, lam_k1 = h/6 lam + h/2 J(Y2)^T lam_k2,
 // where J = df/dy.  f = (u, a(r, theta, u)); the transposed Jacobian of the
-// acceleration is taken in reverse mode through the contraction (kerr_contract,
-// written out below) and in forward mode (dual numbers in r, theta) through the
-// position-dependent coefficients (kerr_coef).  Steps a lane did not take (after
-// it stopped, or a terminal step whose result was discarded) are the identity.
+// acceleration is the hand-written reverse mode of the regrouped acceleration the
+// forward kernels evaluate (kerr_accel_vjp), at the stage points the forward step
+// forms.  Steps a lane did not take (after it stopped, or a terminal step whose result
+// was discarded) are the identity.  The next state of the reverse walk is loaded
+// while the current one is transposed.
 #include "dual.hpp"
 #include "internal.hpp"
 
@@ -34,137 +35,36 @@ struct AdjArgs {
     int32_t N, K;
 };
 
-// dL/d(r, theta, u) of the acceleration given dL/d(at, ar, ath, aph).
-__device__ __forceinline__ void vjp_accel(double M, double a, double r, double th, double ut,
-                                          double ur, double uth, double uph, double b_at,
-                                          double b_ar, double b_ath, double b_aph, double &rbar,
-                                          double &thbar, double ubar[4])
-{
-    typedef Dual2<double> D;
-    double s, c;
-    sincos_any(th, s, c);
-    // pass 1: primal coefficients -> contraction -> cotangents of the coefficients
-    KerrCoef<double> K;
-    kerr_coef<double>(M, a, r, s, c, K);
-    double at, ar, ath, aph;
-    KerrContr<double> X;
-    kerr_contract(K, ut, ur, uth, uph, at, ar, ath, aph, &X);
-
-    KerrCoef<double> B;  // dL/d(coefficient)
-    // at = Rtt Wt - Rtp Wp, aph = Rpp Wp - Rtp Wt
-    B.Rtt = b_at * X.Wt;
-    B.Rtp = -fma(b_at, X.Wp, b_aph * X.Wt);
-    B.Rpp = b_aph * X.Wp;
-    const double bWt = fma(b_at, K.Rtt, -b_aph * K.Rtp);
-    const double bWp = fma(b_aph, K.Rpp, -b_at * K.Rtp);
-    // ar = Fr Dirho2, ath = Fth irho2
-    const double bFr = b_ar * K.Dirho2;
-    B.Dirho2 = b_ar * X.Fr;
-    const double bFth = b_ath * K.irho2;
-    B.irho2 = b_ath * X.Fth;
-    // Fr = Qr - dgrr_r urur + r uthuth + c1 uruth2
-    // Fth = Qth - c1 urur + a2sc uthuth - r uruth2,   uruth2 = 2 ur uth
-    const double urur = ur * ur, uthuth = uth * uth, uruth2 = (ur + ur) * uth;
-    const double bQr = bFr, bQth = bFth;
-    B.dgrr_r = -bFr * urur;
-    B.c1 = fma(bFr, uruth2, -bFth * urur);
-    B.r = fma(bFr, uthuth, -bFth * uruth2);
-    B.a2sc = bFth * uthuth;
-    const double burur = -fma(bFr, K.dgrr_r, bFth * K.c1);
-    const double buthuth = fma(bFr, K.r, bFth * K.a2sc);
-    const double buruth2 = fma(bFr, K.c1, -bFth * K.r);
-    double bur = 2.0 * fma(ur, burur, uth * buruth2);
-    double buth = 2.0 * fma(uth, buthuth, ur * buruth2);
-    // Qr = ut Pt_r + uph Pp_r, Qth = ut Pt_th + uph Pp_th
-    double but = fma(bQr, X.Pt_r, bQth * X.Pt_th);
-    double buph = fma(bQr, X.Pp_r, bQth * X.Pp_th);
-    double bPt_r = bQr * ut, bPp_r = bQr * uph, bPt_th = bQth * ut, bPp_th = bQth * uph;
-    // Wt = ur Pt_r + uth Pt_th, Wp = ur Pp_r + uth Pp_th
-    bur = fma(bWt, X.Pt_r, fma(bWp, X.Pp_r, bur));
-    buth = fma(bWt, X.Pt_th, fma(bWp, X.Pp_th, buth));
-    bPt_r = fma(bWt, ur, bPt_r);
-    bPt_th = fma(bWt, uth, bPt_th);
-    bPp_r = fma(bWp, ur, bPp_r);
-    bPp_th = fma(bWp, uth, bPp_th);
-    // Pt_r = dgtt_r ut + dgtp_r uph, Pt_th = dgtt_th ut + dgtp_th uph,
-    // Pp_r = dgtp_r ut + dgpp_r uph, Pp_th = dgtp_th ut + dgpp_th uph
-    B.dgtt_r = bPt_r * ut;
-    B.dgtp_r = fma(bPt_r, uph, bPp_r * ut);
-    B.dgpp_r = bPp_r * uph;
-    B.dgtt_th = bPt_th * ut;
-    B.dgtp_th = fma(bPt_th, uph, bPp_th * ut);
-    B.dgpp_th = bPp_th * uph;
-    but = fma(bPt_r, K.dgtt_r, fma(bPt_th, K.dgtt_th, fma(bPp_r, K.dgtp_r, fma(bPp_th, K.dgtp_th, but))));
-    buph = fma(bPt_r, K.dgtp_r, fma(bPt_th, K.dgtp_th, fma(bPp_r, K.dgpp_r, fma(bPp_th, K.dgpp_th, buph))));
-    ubar[0] = but;
-    ubar[1] = bur;
-    ubar[2] = buth;
-    ubar[3] = buph;
-    // pass 2: the coefficients again in dual numbers (d/dr, d/dtheta), each folded into
-    // the r and theta cotangents as soon as it is formed
-    KerrCoef<D> Kd;
-    kerr_coef<D>(D(M), D(a), D(r, 1.0, 0.0), D(s, 0.0, c), D(c, 0.0, -s), Kd);
-    double sr = 0.0, st = 0.0;
-#define MALBEC_C(f) sr = fma(B.f, Kd.f.dr, sr); st = fma(B.f, Kd.f.dth, st);
-    MALBEC_C(r) MALBEC_C(Rtt) MALBEC_C(Rtp) MALBEC_C(Rpp) MALBEC_C(irho2)
-    MALBEC_C(Dirho2) MALBEC_C(a2sc) MALBEC_C(dgtt_r) MALBEC_C(dgtt_th) MALBEC_C(dgtp_r)
-    MALBEC_C(dgtp_th) MALBEC_C(dgpp_r) MALBEC_C(dgpp_th) MALBEC_C(dgrr_r) MALBEC_C(c1)
-#undef MALBEC_C
-    rbar = sr;
-    thbar = st;
-}
-
-// mu = J(Y)^T lam_k for f = (u, a): mu_t = mu_phi = 0, mu_{r,theta} from a,
-// mu_u = lam_k[x] + (da/du)^T lam_k[a].  Y = (r, th, ut, ur, uth, uph).
-__device__ __forceinline__ void jt(const Spacetime &S, const double Y[6], const double lk[8], double mu[8])
-{
-    double rbar, thbar, ub[4];
-    vjp_accel(S.M, S.a, Y[0], Y[1], Y[2], Y[3], Y[4], Y[5], lk[4], lk[5], lk[6], lk[7], rbar, thbar, ub);
-    mu[0] = 0.0;
-    mu[1] = rbar;
-    mu[2] = thbar;
-    mu[3] = 0.0;
-    mu[4] = lk[0] + ub[0];
-    mu[5] = lk[1] + ub[1];
-    mu[6] = lk[2] + ub[2];
-    mu[7] = lk[3] + ub[3];
-}
-
-// lam <- (d y_{n+1} / d y_n)^T lam for the RK4 step from y (same stage arithmetic as
-// rk4_stages).
-__device__ __forceinline__ void vjp_step(const Spacetime &S, double h, const double y[8], double lam[8])
-{
-    AccelF64 f{S.M, S.a, {}};
-    const double hh = 0.5 * h;
-    double Y1[6] = {y[1], y[2], y[4], y[5], y[6], y[7]};
-    double at, ar, ath, aph;
-    f(0, Y1[0], Y1[1], Y1[2], Y1[3], Y1[4], Y1[5], at, ar, ath, aph);
-    double Y2[6] = {fma(hh, y[5], y[1]), fma(hh, y[6], y[2]), fma(hh, at, y[4]), fma(hh, ar, y[5]),
-                    fma(hh, ath, y[6]), fma(hh, aph, y[7])};
-    f(1, Y2[0], Y2[1], Y2[2], Y2[3], Y2[4], Y2[5], at, ar, ath, aph);
-    double Y3[6] = {fma(hh, Y2[3], y[1]), fma(hh, Y2[4], y[2]), fma(hh, at, y[4]), fma(hh, ar, y[5]),
-                    fma(hh, ath, y[6]), fma(hh, aph, y[7])};
-    f(2, Y3[0], Y3[1], Y3[2], Y3[3], Y3[4], Y3[5], at, ar, ath, aph);
-    double Y4[6] = {fma(h, Y3[3], y[1]), fma(h, Y3[4], y[2]), fma(h, at, y[4]), fma(h, ar, y[5]),
-                    fma(h, ath, y[6]), fma(h, aph, y[7])};
-
-    const double h6 = h * (1.0 / 6.0), h3 = 2.0 * h6;
-    double ly[8], lk[8], mu[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) { ly[k] = lam[k]; lk[k] = h6 * lam[k]; }
-    jt(S, Y4, lk, mu);  // k4
-#pragma unroll
-    for (int k = 0; k < 8; ++k) { ly[k] += mu[k]; lk[k] = fma(h3, lam[k], h * mu[k]); }
-    jt(S, Y3, lk, mu);  // k3
-#pragma unroll
-    for (int k = 0; k < 8; ++k) { ly[k] += mu[k]; lk[k] = fma(h3, lam[k], hh * mu[k]); }
-    jt(S, Y2, lk, mu);  // k2
-#pragma unroll
-    for (int k = 0; k < 8; ++k) { ly[k] += mu[k]; lk[k] = fma(h6, lam[k], hh * mu[k]); }
-    jt(S, Y1, lk, mu);  // k1
-#pragma unroll
-    for (int k = 0; k < 8; ++k) lam[k] = ly[k] + mu[k];
-}
+// The acceleration of the forward kernels (the same stage trigonometry: a fresh sin
+// and cos at the step's start, short rotations at the later stages) with its
+// transposed Jacobian for rk4_vjp.  The stage points and the sin and cos of each (the
+// last stage's formed by prepare) are kept from the forward pass, so the reverse pass
+// evaluates no trigonometry.  (Keeping them in LDS instead of registers, to lower the
+// register count, measured 4 % slower at the one wave per SIMD that 65,536 lanes give.)
+struct AdjAccel {
+    double M, a;
+    StageTrigT<true> trig;
+    double Ys[4][6], sk[4], ck[4];
+    __device__ __forceinline__ double &Y(int st, int k) { return Ys[st][k]; }
+    __device__ __forceinline__ void keep() {}
+    __device__ __forceinline__ void operator()(int stage, double r, double th, double ut, double ur,
+                                               double uth, double uph, double &at, double &ar,
+                                               double &ath, double &aph)
+    {
+        trig(stage, th, sk[stage], ck[stage]);
+        kerr_accel<double>(M, a, r, sk[stage], ck[stage], ut, ur, uth, uph, at, ar, ath, aph);
+    }
+    __device__ __forceinline__ void prepare(int stage, double th) { trig(stage, th, sk[stage], ck[stage]); }
+    __device__ __forceinline__ void vjp(int stage, double r, double, double ut, double ur, double uth,
+                                        double uph, double bat, double bar, double bath, double baph,
+                                        double &rb, double &thb, double ub[4])
+    {
+        const double s = sk[stage], c = ck[stage];
+        double sb, cb;
+        kerr_accel_vjp<double>(M, a, r, s, c, ut, ur, uth, uph, bat, bar, bath, baph, rb, sb, cb, ub);
+        thb = fma(sb, c, -cb * s);  // d/dtheta through s = sin theta, c = cos theta
+    }
+};
 
 template <bool MULTI>
 __global__ void __launch_bounds__(256) adjoint_kernel(AdjArgs A, StTable T)
@@ -208,10 +108,17 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjArgs A, StTable T)
                 for (int k = 0; k < 8; ++k) y[k] = y1[k];
             }
         }
-        // reverse sweep
+        // reverse sweep; yn holds the state of step j, loaded one step ahead
+        double yn[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) yn[k] = A.scratch[((int64_t)(len - 1) * 8 + k) * n + i];
         for (int32_t j = len - 1; j >= 0; --j) {
 #pragma unroll
-            for (int k = 0; k < 8; ++k) y[k] = A.scratch[((int64_t)j * 8 + k) * n + i];
+            for (int k = 0; k < 8; ++k) y[k] = yn[k];
+            if (j > 0) {
+#pragma unroll
+                for (int k = 0; k < 8; ++k) yn[k] = A.scratch[((int64_t)(j - 1) * 8 + k) * n + i];
+            }
             bool accepted = true;
             if (g0 + j == taken - 1 && status != kActive) {
                 // terminal step: its result was kept only if the termination rule accepted it
@@ -219,7 +126,10 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjArgs A, StTable T)
                 rk4_step_f64(S, A.h, y, y1, sr);
                 terminate_f64(S, A.r_escape, sr, y1, accepted);
             }
-            if (accepted) vjp_step(S, A.h, y, lam);
+            if (accepted) {
+                AdjAccel f{S.M, S.a, {}, {}, {}, {}};
+                rk4_vjp(f, A.h, y, lam);
+            }
         }
     }
 #pragma unroll

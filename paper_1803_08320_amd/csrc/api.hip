@@ -116,7 +116,8 @@ int malbec_version(void) { return 10000 * 0 + 100 * 3 + 0; }
 
 size_t malbec_workspace_bytes(int32_t op, int64_t n, int32_t aux)
 {
-    if (op == MALBEC_OP_CAMERA) return 256;  // work counter (own cache line)
+    if (op == MALBEC_OP_CAMERA && n >= 0)  // work counter (own cache line), then the rays' initial states
+        return 256 + (size_t)n * 8 * sizeof(double);
     if (op == MALBEC_OP_ADAPTIVE && aux == 2 && n >= 0)
         return 256 + sched_layout(n).bytes;  // work counter, then the periapsis order
     if ((op == MALBEC_OP_INTEGRATE || op == MALBEC_OP_ADAPTIVE) && aux)

@@ -6,8 +6,16 @@
 // 64 rays in flight and, after every sub-chunk of steps, retires the lanes whose
 // ray ended (ballot of the finished lanes) and refills them from a global work
 // counter with one atomic per wavefront (mbcnt prefix over the idle-lane mask
-// gives each idle lane its slot).  A lane's result depends only on its pixel, so
-// the persistent and the one-thread-per-pixel kernels give identical bits.
+// gives each idle lane its slot).  The rays' initial states are formed beforehand by
+// one thread per pixel into the workspace (64 B per pixel, read back once when the
+// pixel is taken), which keeps the image-plane arithmetic out of the persistent
+// loop and its registers: the loop fits the 128 registers of four waves per SIMD,
+// as the one-thread-per-pixel kernel does.  A lane's result depends only on its
+// pixel, so the persistent and the one-thread-per-pixel kernels give identical bits.
+// Finished rays write their results straight to their pixels' slots: a ray's 24 B
+// of results (status, step count, crossing) against its hundreds of steps make the
+// scattered writes a negligible share of the traffic, so no staging of results in
+// LDS is needed.
 #include "ic_device.hpp"
 #include "internal.hpp"
 
@@ -117,11 +125,23 @@ __global__ void __launch_bounds__(256) camera_plain_kernel(CamArgs A)
     write_result(A, p, st, n, rc, pc, y);
 }
 
+// Initial states of all rays, component-major y0[k * npix + p].
+__global__ void __launch_bounds__(256) camera_rays_kernel(CamArgs A, double *y0)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= A.npix) return;
+    double y[8];
+    pixel_ray(A, p, y);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) y0[k * A.npix + p] = y[k];
+}
+
 // Persistent kernel: every wavefront loops until the work counter passes npix and
 // all of its lanes are idle; each lane's ray ends within max_steps steps, so every
-// wavefront exits.
+// wavefront exits.  y0: the rays' initial states (camera_rays_kernel).
 __global__ void __launch_bounds__(256) camera_persistent_kernel(CamArgs A,
-                                                                unsigned long long *counter)
+                                                                unsigned long long *counter,
+                                                                const double *y0)
 {
     const unsigned lane = threadIdx.x & 63u;
     int64_t p = -1;  // pixel in flight, -1 = idle
@@ -144,7 +164,8 @@ __global__ void __launch_bounds__(256) camera_persistent_kernel(CamArgs A,
                 const unsigned long long id = base + rank;
                 if (id < (unsigned long long)A.npix) {
                     p = (int64_t)id;
-                    pixel_ray(A, p, y);
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) y[k] = y0[k * A.npix + p];
                     n = 0;
                     rc = __builtin_nan("");
                     pc = __builtin_nan("");
@@ -153,15 +174,12 @@ __global__ void __launch_bounds__(256) camera_persistent_kernel(CamArgs A,
         }
         if (__ballot(p >= 0) == 0ull) break;  // nothing in flight and nothing to fetch
         if (p >= 0) {
-            for (int32_t s = 0; s < A.chunk; ++s) {
-                int32_t st;
-                if (n >= A.max_steps) st = kBudget;
-                else st = camera_step(A, y, n, rc, pc);
-                if (st != kActive) {
-                    write_result(A, p, st, n, rc, pc, y);
-                    p = -1;
-                    break;
-                }
+            int32_t st = kActive;
+            for (int32_t s = 0; s < A.chunk && st == kActive; ++s)
+                st = n >= A.max_steps ? kBudget : camera_step(A, y, n, rc, pc);
+            if (st != kActive) {
+                write_result(A, p, st, n, rc, pc, y);
+                p = -1;
             }
         }
     }
@@ -218,9 +236,13 @@ int launch_camera(const malbec_camera &cam, double r_stop, double disk_r_in, int
     const int64_t need = (A.npix + block - 1) / block;  // no more lanes than pixels
     if (grid > need) grid = need;
     unsigned long long *counter = (unsigned long long *)ws;
+    double *y0 = (double *)((char *)ws + 256);
+    hipLaunchKernelGGL(camera_rays_kernel, dim3(grid_for(A.npix, 256)), dim3(256), 0, s, A, y0);
+    MALBEC_LAUNCH_CHECK("camera_rays_kernel");
     hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(1), 0, s, counter);
     MALBEC_LAUNCH_CHECK("zero_counter_kernel");
-    hipLaunchKernelGGL(camera_persistent_kernel, dim3((unsigned)grid), dim3(block), 0, s, A, counter);
+    hipLaunchKernelGGL(camera_persistent_kernel, dim3((unsigned)grid), dim3(block), 0, s, A, counter,
+                       (const double *)y0);
     MALBEC_LAUNCH_CHECK("camera_persistent_kernel");
     return MALBEC_OK;
 }

@@ -109,10 +109,8 @@ __device__ __forceinline__ void contract_row(const V *f, double wra, double dwra
     }
 }
 
-// The same for float node values, through the lane's stencil cache (C), refilled
-// when the cell changes.
 // F, dF/dr, dF/dtheta of the five functions at (r, theta), through the lane's stencil
-// cache C (refilled from the grid when the cell changes).
+// cache C (refilled from the grid when the cell changes; double or float node values).
 template <typename Node>
 __device__ __forceinline__ void grid_eval(const GridArgs &A, double r, double th, double F[5],
                                           double Fr[5], double Ft[5], StencilCache<Node> *C)
@@ -167,7 +165,6 @@ template <typename Node>
 struct GridHam {
     const GridArgs &A;
     const HamConst<double> &P;
-    // the lane's stencil cache (float node values only)
     StencilCache<Node> *C;  // the lane's stencil cache
     StageTrig trig;
     double st_r[4], st_th[4];

@@ -53,7 +53,10 @@ __device__ __forceinline__ void step_f64(const Spacetime &S, const HamConst<doub
         rk4_step_f64(S, h, y, y1, sr);
 }
 
-template <bool MULTI, bool CKPT, bool HAM>
+// UNIT_M: the batch's one spacetime has M = 1 (the unit of the paper's runs), known at
+// compile time, which removes the multiplications by M (exact: the results are the
+// bits of the general kernel).
+template <bool MULTI, bool CKPT, bool HAM, bool UNIT_M = false>
 __global__ void __launch_bounds__(256) rk4_f64_kernel(IntArgs A, StTable T)
 {
     __shared__ Spacetime lds_st[kMaxSt];
@@ -73,7 +76,8 @@ __global__ void __launch_bounds__(256) rk4_f64_kernel(IntArgs A, StTable T)
             A.status[i] = st;
         }
     }
-    const Spacetime S = MULTI ? lds_st[sid] : T.st[0];
+    Spacetime S = MULTI ? lds_st[sid] : T.st[0];
+    if (UNIT_M) S.M = 1.0;
     // first thread of this wavefront (wave-uniform, held in a scalar register)
     const int32_t wave0 = __builtin_amdgcn_readfirstlane((int32_t)threadIdx.x) & ~63;
 
@@ -229,7 +233,8 @@ __global__ void __launch_bounds__(256) rk4_f64_monitor_kernel(IntArgs A, StTable
     __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= A.n) return;
-    MonProg<F64Prog<HAM>, HAM> P{F64Prog<HAM>{A, lds_st, multi != 0, T.n_st}, MA};
+    __shared__ double lds_mon[8 * kMonLanes];
+    MonProg<F64Prog<HAM>, HAM> P{F64Prog<HAM>{A, lds_st, multi != 0, T.n_st}, MA, &lds_mon[threadIdx.x]};
     typename MonProg<F64Prog<HAM>, HAM>::Lane L;
     if (!P.load(i, L)) return;
     while (!P.step(L)) {
@@ -246,7 +251,8 @@ __global__ void __launch_bounds__(256) rk4_f64_monitor_persistent_kernel(IntArgs
     __shared__ Spacetime lds_st[kMaxSt];
     for (int k = threadIdx.x; k < T.n_st; k += blockDim.x) lds_st[k] = T.st[k];
     __syncthreads();
-    MonProg<F64Prog<HAM>, HAM> P{F64Prog<HAM>{A, lds_st, multi != 0, T.n_st}, MA};
+    __shared__ double lds_mon[8 * kMonLanes];
+    MonProg<F64Prog<HAM>, HAM> P{F64Prog<HAM>{A, lds_st, multi != 0, T.n_st}, MA, &lds_mon[threadIdx.x]};
     persistent_loop(P, A.n, counter, chunk);
 }
 
@@ -274,8 +280,12 @@ int launch_monitor(const IntArgs &A, const StTable &T, const MonArgs &MA, bool m
 template <bool MULTI, bool CKPT, bool HAM>
 int launch_kernel(const IntArgs &A, const StTable &T, int block, hipStream_t s)
 {
-    hipLaunchKernelGGL((rk4_f64_kernel<MULTI, CKPT, HAM>), dim3(grid_for(A.n, block)), dim3(block), 0,
-                       s, A, T);
+    if (!MULTI && !CKPT && T.st[0].M == 1.0)
+        hipLaunchKernelGGL((rk4_f64_kernel<false, false, HAM, true>), dim3(grid_for(A.n, block)),
+                           dim3(block), 0, s, A, T);
+    else
+        hipLaunchKernelGGL((rk4_f64_kernel<MULTI, CKPT, HAM>), dim3(grid_for(A.n, block)), dim3(block),
+                           0, s, A, T);
     MALBEC_LAUNCH_CHECK("rk4_f64_kernel");
     return MALBEC_OK;
 }

@@ -213,6 +213,202 @@ MALBEC_HD inline void kerr_accel(T M, T a, T r, T s, T c, T ut, T ur, T uth, T u
     ath = fma(irho2, fma(-r, uruth2, Qth), k1 * fma(-iDelta, urur, uthuth));
 }
 
+// Reverse mode of kerr_accel: given the cotangents (bat, bar, bath, baph) of
+// (a^t, a^r, a^theta, a^phi), the cotangents of r, s = sin theta, c = cos theta and
+// of the 4-velocity (ub[0..3] for u^t, u^r, u^theta, u^phi), i.e. the transposed
+// Jacobian of the computed expression applied to b.  The forward expressions are
+// those of kerr_accel, recomputed here; each reverse step below transposes one of them
+// (x = f(y, z) adds xb df/dy to yb and xb df/dz to zb).  M and a are constants.
+template <typename T>
+MALBEC_HD inline void kerr_accel_vjp(T M, T a, T r, T s, T c, T ut, T ur, T uth, T uph, T bat,
+                                     T bar, T bath, T baph, T &rb, T &sb, T &cb, T ub[4])
+{
+    const T a2 = a * a;
+    const T s2 = s * s;
+    const T sc = s * c;
+    const T r2 = r * r;
+    const T A = r2 + a2;
+    const T rho2 = fma(a2, c * c, r2);
+    const T M2 = M + M;
+    const T Delta = fma(-M2, r, A);
+    const T Ds2 = Delta * s2;
+    const T inv = recip(rho2 * Ds2);
+    const T iDs2 = inv * rho2;
+    const T irho2 = inv * Ds2;
+    const T iDelta = iDs2 * s2;
+    const T ri = r * irho2;
+    const T q = M2 * ri;
+    const T hdq_r = fma(-q, ri, M * irho2);
+    const T a2sc = a2 * sc;
+    const T k1 = a2sc * irho2;
+    const T hdq_th = q * k1;
+    const T aq = -a * q;
+    const T as2n = -a * s2;
+    const T aqsc = aq * sc;
+    const T V = fma(as2n, uph, ut);
+    const T Pt_r = hdq_r * V;
+    const T Pt_th = fma(hdq_th, V, aqsc * uph);
+    const T rs2 = r * s2;
+    const T X_r = rs2 * uph;
+    const T Asc = A * sc;
+    const T X_th = fma(aqsc, V, Asc * uph);
+    const T Wt = fma(ur, Pt_r, uth * Pt_th);
+    const T Y = fma(ur, X_r, uth * X_th);
+    const T Qr = fma(Pt_r, V, uph * X_r);
+    const T Qth = fma(Pt_th, V, uph * X_th);
+    const T urur = ur * ur, uthuth = uth * uth, uruth2 = (ur + ur) * uth;
+    const T iDelta2 = iDelta + iDelta;
+    const T T1 = fma(A, Wt, -aq * Y);           // a^t = iDelta2 T1
+    const T aiD2 = a * iDelta2;
+    const T q2m2 = fma(T(2), q, T(-2));
+    const T C2 = iDs2 * q2m2;                   // a^phi = aiD2 Wt + C2 Y
+    const T rmM = r - M;
+    const T e_rr = fma(-iDelta, rmM, ri);
+    const T DI = Delta * irho2;
+    const T G = fma(r, uthuth, Qr);             // a^r = k1 uruth2 - e_rr urur + DI G
+    const T H = fma(-r, uruth2, Qth);           // a^theta = irho2 H + k1 Kk
+    const T Kk = fma(-iDelta, urur, uthuth);
+
+    // a^theta = irho2 H + k1 Kk
+    T irho2b = bath * H;
+    const T Hb = bath * irho2;
+    T k1b = bath * Kk;
+    const T Kkb = bath * k1;
+    // Kk = uthuth - iDelta urur
+    T iDeltab = -Kkb * urur;
+    T ururb = -Kkb * iDelta;
+    T uthuthb = Kkb;
+    // H = Qth - r uruth2
+    T rbar = -Hb * uruth2;
+    T uruth2b = -Hb * r;
+    const T Qthb = Hb;
+    // a^r = k1 uruth2 - e_rr urur + DI G
+    k1b = fma(bar, uruth2, k1b);
+    uruth2b = fma(bar, k1, uruth2b);
+    const T e_rrb = -bar * urur;
+    ururb = fma(-bar, e_rr, ururb);
+    const T DIb = bar * G;
+    const T Gb = bar * DI;
+    // G = r uthuth + Qr
+    rbar = fma(Gb, uthuth, rbar);
+    uthuthb = fma(Gb, r, uthuthb);
+    const T Qrb = Gb;
+    // DI = Delta irho2
+    T Deltab = DIb * irho2;
+    irho2b = fma(DIb, Delta, irho2b);
+    // e_rr = ri - iDelta (r - M)
+    iDeltab = fma(-e_rrb, rmM, iDeltab);
+    rbar = fma(-e_rrb, iDelta, rbar);
+    T rib = e_rrb;
+    // a^phi = aiD2 Wt + C2 Y, aiD2 = a iDelta2
+    T iDelta2b = a * (baph * Wt);
+    T Wtb = baph * aiD2;
+    const T C2b = baph * Y;
+    T Yb = baph * C2;
+    // C2 = iDs2 (2 q - 2)
+    T iDs2b = C2b * q2m2;
+    T qb = (C2b + C2b) * iDs2;
+    // a^t = iDelta2 T1
+    iDelta2b = fma(bat, T1, iDelta2b);
+    const T T1b = bat * iDelta2;
+    // T1 = A Wt - aq Y
+    T Ab = T1b * Wt;
+    Wtb = fma(T1b, A, Wtb);
+    T aqb = -T1b * Y;
+    Yb = fma(-T1b, aq, Yb);
+    // iDelta2 = 2 iDelta
+    iDeltab = fma(T(2), iDelta2b, iDeltab);
+    // Qth = Pt_th V + uph X_th
+    T Pt_thb = Qthb * V;
+    T Vb = Qthb * Pt_th;
+    T uphb = Qthb * X_th;
+    T X_thb = Qthb * uph;
+    // Qr = Pt_r V + uph X_r
+    T Pt_rb = Qrb * V;
+    Vb = fma(Qrb, Pt_r, Vb);
+    uphb = fma(Qrb, X_r, uphb);
+    T X_rb = Qrb * uph;
+    // Y = ur X_r + uth X_th
+    T urb = Yb * X_r;
+    X_rb = fma(Yb, ur, X_rb);
+    T uthb = Yb * X_th;
+    X_thb = fma(Yb, uth, X_thb);
+    // Wt = ur Pt_r + uth Pt_th
+    urb = fma(Wtb, Pt_r, urb);
+    Pt_rb = fma(Wtb, ur, Pt_rb);
+    uthb = fma(Wtb, Pt_th, uthb);
+    Pt_thb = fma(Wtb, uth, Pt_thb);
+    // X_th = aqsc V + Asc uph, Asc = A sc
+    T aqscb = X_thb * V;
+    Vb = fma(X_thb, aqsc, Vb);
+    const T Ascb = X_thb * uph;
+    uphb = fma(X_thb, Asc, uphb);
+    Ab = fma(Ascb, sc, Ab);
+    T scb = Ascb * A;
+    // X_r = rs2 uph, rs2 = r s2
+    const T rs2b = X_rb * uph;
+    uphb = fma(X_rb, rs2, uphb);
+    rbar = fma(rs2b, s2, rbar);
+    T s2b = rs2b * r;
+    // Pt_th = hdq_th V + aqsc uph
+    const T hdq_thb = Pt_thb * V;
+    Vb = fma(Pt_thb, hdq_th, Vb);
+    aqscb = fma(Pt_thb, uph, aqscb);
+    uphb = fma(Pt_thb, aqsc, uphb);
+    // Pt_r = hdq_r V
+    const T hdq_rb = Pt_rb * V;
+    Vb = fma(Pt_rb, hdq_r, Vb);
+    // V = ut + as2n uph
+    const T as2nb = Vb * uph;
+    uphb = fma(Vb, as2n, uphb);
+    // aqsc = aq sc, as2n = -a s2, aq = -a q
+    aqb = fma(aqscb, sc, aqb);
+    scb = fma(aqscb, aq, scb);
+    s2b = fma(-a, as2nb, s2b);
+    qb = fma(-a, aqb, qb);
+    // hdq_th = q k1
+    qb = fma(hdq_thb, k1, qb);
+    k1b = fma(hdq_thb, q, k1b);
+    // k1 = a2sc irho2, a2sc = a^2 sc
+    scb = fma(a2 * k1b, irho2, scb);
+    irho2b = fma(k1b, a2sc, irho2b);
+    // hdq_r = M irho2 - q ri
+    qb = fma(-hdq_rb, ri, qb);
+    rib = fma(-hdq_rb, q, rib);
+    irho2b = fma(hdq_rb, M, irho2b);
+    // q = M2 ri, ri = r irho2
+    rib = fma(qb, M2, rib);
+    rbar = fma(rib, irho2, rbar);
+    irho2b = fma(rib, r, irho2b);
+    // iDelta = iDs2 s2
+    iDs2b = fma(iDeltab, s2, iDs2b);
+    s2b = fma(iDeltab, iDs2, s2b);
+    // irho2 = inv Ds2, iDs2 = inv rho2, inv = 1 / (rho2 Ds2)
+    const T invb = fma(irho2b, Ds2, iDs2b * rho2);
+    T Ds2b = irho2b * inv;
+    T rho2b = iDs2b * inv;
+    const T P0b = -invb * (inv * inv);
+    rho2b = fma(P0b, Ds2, rho2b);
+    Ds2b = fma(P0b, rho2, Ds2b);
+    // Ds2 = Delta s2
+    Deltab = fma(Ds2b, s2, Deltab);
+    s2b = fma(Ds2b, Delta, s2b);
+    // Delta = A - M2 r
+    rbar = fma(-M2, Deltab, rbar);
+    Ab = Ab + Deltab;
+    // rho2 = r2 + a2 c^2, A = r2 + a2, r2 = r r
+    rbar = fma(r + r, rho2b + Ab, rbar);
+    // s2 = s s, sc = s c, c^2
+    sb = fma(scb, c, (s + s) * s2b);
+    cb = fma(scb, s, (c + c) * (a2 * rho2b));
+    rb = rbar;
+    // urur, uthuth, uruth2 = 2 ur uth
+    ub[0] = Vb;
+    ub[1] = fma(ur + ur, ururb, fma(uth + uth, uruth2b, urb));
+    ub[2] = fma(uth + uth, uthuthb, fma(ur + ur, uruth2b, uthb));
+    ub[3] = uphb;
+}
+
 // The direct form: coefficients, then contraction, as the adjoint differentiates it.
 template <typename T>
 MALBEC_HD inline void kerr_accel_direct(T M, T a, T r, T s, T c, T ut, T ur, T uth, T uph, T &at,
@@ -298,6 +494,75 @@ MALBEC_HD inline void rk4_delta(Accel &accel, T h, const T y[8], T d[8], T sr[3]
     const T h6 = h * T(1.0 / 6.0);
 #pragma unroll
     for (int k = 0; k < 8; ++k) d[k] = h6 * acc[k];
+}
+
+// Transposed RK4 step: lam <- (d y1 / d y)^T lam for the step y -> y1 of rk4_step.
+// With k_i = f(Y_i), Y_1 = y, Y_2 = y + h/2 k_1, Y_3 = y + h/2 k_2, Y_4 = y + h k_3 and
+// y1 = y + h/6 (k_1 + 2 k_2 + 2 k_3 + k_4), the cotangents of the stage values are
+//   lk_4 = h/6 lam,  lk_3 = h/3 lam + h J_4^T lk_4,
+//   lk_2 = h/3 lam + h/2 J_3^T lk_3,  lk_1 = h/6 lam + h/2 J_2^T lk_2,
+// and lam_y = lam + sum_i J_i^T lk_i, where J_i = df/dy at Y_i.  f = (u, a(r, theta, u)),
+// so J^T lk has no t or phi component, (da/d(r, theta))^T lk_a in r and theta, and
+// lk_x + (da/du)^T lk_a in u.  F supplies the forward stage accelerations exactly as
+// rk4_stages forms them (operator()), the trigonometry of the last stage point
+// (prepare(3, theta)), the transposed Jacobian of the acceleration at a stage point
+// (vjp(stage, ...), returning the cotangents of r, theta and u), and the storage of the
+// stage points between the two passes (Y(stage, k), k = r, theta, u^t, u^r, u^theta,
+// u^phi; keep() between the passes, after which they are read back from that storage).
+template <typename T, typename F>
+MALBEC_HD inline void rk4_vjp(F &f, T h, const T y[8], T lam[8])
+{
+    const T hh = T(0.5) * h;
+    T at, ar, ath, aph;
+    {
+        T r = y[1], th = y[2], ut = y[4], ur = y[5], uth = y[6], uph = y[7];
+        f.Y(0, 0) = r; f.Y(0, 1) = th; f.Y(0, 2) = ut; f.Y(0, 3) = ur; f.Y(0, 4) = uth; f.Y(0, 5) = uph;
+        f(0, r, th, ut, ur, uth, uph, at, ar, ath, aph);
+        r = fma(hh, y[5], y[1]); th = fma(hh, y[6], y[2]);
+        ut = fma(hh, at, y[4]); ur = fma(hh, ar, y[5]); uth = fma(hh, ath, y[6]); uph = fma(hh, aph, y[7]);
+        f.Y(1, 0) = r; f.Y(1, 1) = th; f.Y(1, 2) = ut; f.Y(1, 3) = ur; f.Y(1, 4) = uth; f.Y(1, 5) = uph;
+        f(1, r, th, ut, ur, uth, uph, at, ar, ath, aph);
+        r = fma(hh, ur, y[1]); th = fma(hh, uth, y[2]);
+        ut = fma(hh, at, y[4]); ur = fma(hh, ar, y[5]); uth = fma(hh, ath, y[6]); uph = fma(hh, aph, y[7]);
+        f.Y(2, 0) = r; f.Y(2, 1) = th; f.Y(2, 2) = ut; f.Y(2, 3) = ur; f.Y(2, 4) = uth; f.Y(2, 5) = uph;
+        f(2, r, th, ut, ur, uth, uph, at, ar, ath, aph);
+        r = fma(h, ur, y[1]); th = fma(h, uth, y[2]);
+        ut = fma(h, at, y[4]); ur = fma(h, ar, y[5]); uth = fma(h, ath, y[6]); uph = fma(h, aph, y[7]);
+        f.Y(3, 0) = r; f.Y(3, 1) = th; f.Y(3, 2) = ut; f.Y(3, 3) = ur; f.Y(3, 4) = uth; f.Y(3, 5) = uph;
+        f.prepare(3, th);
+    }
+    f.keep();
+
+    const T h6 = h * T(1.0 / 6.0), h3 = T(2) * h6;
+    T ly[8], lk[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) { ly[k] = lam[k]; lk[k] = h6 * lam[k]; }
+#pragma unroll
+    for (int st = 3; st >= 0; --st) {
+        // mu = J(Y_st)^T lk
+        T mr, mth, mu[4];
+        f.vjp(st, f.Y(st, 0), f.Y(st, 1), f.Y(st, 2), f.Y(st, 3), f.Y(st, 4), f.Y(st, 5), lk[4],
+              lk[5], lk[6], lk[7], mr, mth, mu);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) mu[k] += lk[k];
+        ly[1] += mr;
+        ly[2] += mth;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) ly[4 + k] += mu[k];
+        if (st > 0) {
+            // lk of the previous stage: its weight times lam plus its offset coefficient times mu
+            const T w = st == 1 ? h6 : h3;
+            const T o = st == 3 ? h : hh;
+            lk[0] = w * lam[0];
+            lk[1] = fma(o, mr, w * lam[1]);
+            lk[2] = fma(o, mth, w * lam[2]);
+            lk[3] = w * lam[3];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) lk[4 + k] = fma(o, mu[k], w * lam[4 + k]);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) lam[k] = ly[k];
 }
 
 }  // namespace malbec

@@ -257,7 +257,8 @@ __global__ void __launch_bounds__(256) rk4_f32k_monitor_kernel(MixArgs A, StTabl
     __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= A.n) return;
-    MonProg<MixProg<HAM>, HAM> P{MixProg<HAM>{A, lds_st, multi != 0, T.n_st}, MA};
+    __shared__ double lds_mon[8 * kMonLanes];
+    MonProg<MixProg<HAM>, HAM> P{MixProg<HAM>{A, lds_st, multi != 0, T.n_st}, MA, &lds_mon[threadIdx.x]};
     typename MonProg<MixProg<HAM>, HAM>::Lane L;
     if (!P.load(i, L)) return;
     while (!P.step(L)) {
@@ -274,7 +275,8 @@ __global__ void __launch_bounds__(256) rk4_f32k_monitor_persistent_kernel(MixArg
     __shared__ Spacetime lds_st[kMaxSt];
     for (int k = threadIdx.x; k < T.n_st; k += blockDim.x) lds_st[k] = T.st[k];
     __syncthreads();
-    MonProg<MixProg<HAM>, HAM> P{MixProg<HAM>{A, lds_st, multi != 0, T.n_st}, MA};
+    __shared__ double lds_mon[8 * kMonLanes];
+    MonProg<MixProg<HAM>, HAM> P{MixProg<HAM>{A, lds_st, multi != 0, T.n_st}, MA, &lds_mon[threadIdx.x]};
     persistent_loop(P, A.n, counter, chunk);
 }
 

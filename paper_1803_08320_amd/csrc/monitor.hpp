@@ -71,12 +71,19 @@ struct MonArgs {
 // Base provides the Prog interface plus
 //   static void state64(const Lane&, double y[8])   -- the lane's state in FP64
 //   Lane::S                                         -- the lane's Spacetime
-// I_0 and the running maxima stay in the monitor buffer (read and written at the
-// monitored steps only, 96 B per lane every K steps), not in registers.
+// While a lane is in flight its I_0 and running maxima live in the thread's slot of
+// an LDS array (8 doubles per thread, the block's threads interleaved: kMonLanes
+// apart), not in registers and not in the monitor buffer: the buffer is read when the
+// lane is taken (unless reset) and written when it is stored, once per launch, so
+// the monitored steps add no memory traffic (the persistent kernels take lanes
+// scattered over the batch, where each 8-byte access of the component-major buffer
+// would fetch a cache line of its own).
+constexpr int kMonLanes = 256;  // block size bound of the monitored kernels
 template <class Base, bool HAM>
 struct MonProg {
     Base base;
     MonArgs M;
+    double *slot;  // this thread's LDS slot: value k at slot[k * kMonLanes]
     struct Lane {
         typename Base::Lane b;
         int64_t i;     // the lane's index in the batch
@@ -92,9 +99,12 @@ struct MonProg {
             lane_invariants<HAM>(L.b.S.M, L.b.S.a, y, I0);
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                M.mon[k * M.n + i] = I0[k];
-                M.mon[(4 + k) * M.n + i] = 0.0;
+                slot[k * kMonLanes] = I0[k];
+                slot[(4 + k) * kMonLanes] = 0.0;
             }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) slot[k * kMonLanes] = M.mon[k * M.n + i];
         }
         L.i = i;
         const int32_t r = s0 % M.every;
@@ -109,16 +119,21 @@ struct MonProg {
             double y[8], I[4];
             Base::state64(L.b, y);
             lane_invariants<HAM>(L.b.S.M, L.b.S.a, y, I);
-            const int64_t i = opaque(L.i);
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                double &D = M.mon[(4 + k) * M.n + i];
-                D = fmax(D, fabs(I[k] - M.mon[k * M.n + i]));
+                double &D = slot[(4 + k) * kMonLanes];
+                D = fmax(D, fabs(I[k] - slot[k * kMonLanes]));
             }
         }
         return done;
     }
-    __device__ __forceinline__ void store(int64_t item, const Lane &L) { base.store(item, L.b); }
+    __device__ __forceinline__ void store(int64_t item, const Lane &L)
+    {
+        base.store(item, L.b);
+        const int64_t i = opaque(L.i);
+#pragma unroll
+        for (int k = M.reset ? 0 : 4; k < 8; ++k) M.mon[k * M.n + i] = slot[k * kMonLanes];
+    }
 };
 
 }  // namespace malbec

@@ -137,10 +137,15 @@ def test_hamiltonian_persistent_and_chunked_are_bitwise(m, orc):
     assert (plain[1] == 1).sum() > 50
     for x, y, w in zip(plain, pers, chunk):
         assert np.array_equal(x, y) and np.array_equal(x, w)
-    # parity per spacetime of the mixed batch
+    # parity per spacetime of the mixed batch; a uniform launch of the lanes of one
+    # spacetime (the kernel specialised for M = 1) gives the mixed launch's bits
     for k in range(16):
         sel = np.flatnonzero(st_of_lane == k)
         stk = [sts[k]]
+        if k in (0, 7, 15):
+            one = run_ham(m, stk, z0[:, sel], 0.02, 2500)
+            for x, y in zip(one, plain):
+                assert np.array_equal(x, y[..., sel])
         ref = orc.integrate(stk, z0[:, sel], 0.02, 2500, hamiltonian=True)
         compare(orc, stk, z0[:, sel], plain[0][:, sel], plain[1][sel], plain[2][sel], *ref,
                 rerun_ham(orc, stk, 0.02, 2500))

@@ -45,6 +45,38 @@ extern "C" void chr_rhs_direct(double M, double a, const double *y, double *f) {
     malbec::kerr_accel_direct<double>(M, a, y[1], std::sin(y[2]), std::cos(y[2]), y[4], y[5],
                                       y[6], y[7], f[4], f[5], f[6], f[7]);
 }
+// The acceleration with its transposed Jacobian, for rk4_vjp (host trigonometry).
+struct ChrVjp {
+    double M, a;
+    void operator()(int, double r, double th, double ut, double ur, double uth, double uph,
+                    double &at, double &ar, double &ath, double &aph) const {
+        malbec::kerr_accel<double>(M, a, r, std::sin(th), std::cos(th), ut, ur, uth, uph,
+                                   at, ar, ath, aph);
+    }
+    double Ys[4][6];
+    double &Y(int st, int k) { return Ys[st][k]; }
+    void keep() const {}
+    void prepare(int, double) const {}
+    void vjp(int, double r, double th, double ut, double ur, double uth, double uph, double bat,
+             double bar, double bath, double baph, double &rb, double &thb, double ub[4]) const {
+        const double s = std::sin(th), c = std::cos(th);
+        double sb, cb;
+        malbec::kerr_accel_vjp<double>(M, a, r, s, c, ut, ur, uth, uph, bat, bar, bath, baph,
+                                       rb, sb, cb, ub);
+        thb = sb * c - cb * s;
+    }
+};
+// y^T-side of one acceleration: out = (d a / d(r, theta, u))^T b, 6 values
+extern "C" void chr_accel_vjp(double M, double a, const double *y, const double *b, double *out) {
+    double ub[4];
+    ChrVjp{M, a}.vjp(0, y[1], y[2], y[4], y[5], y[6], y[7], b[0], b[1], b[2], b[3], out[0],
+                     out[1], ub);
+    for (int k = 0; k < 4; ++k) out[2 + k] = ub[k];
+}
+extern "C" void chr_step_vjp(double M, double a, double h, const double *y, double *lam) {
+    ChrVjp f{M, a};
+    malbec::rk4_vjp(f, h, y, lam);
+}
 extern "C" void ham_rhs(double M, double a, const double *z, double *f) {
     Ham h{M, a, malbec::ham_const(a, z[4], z[7])};
     h(0, z[1], z[2], z[5], z[6], f[0], f[1], f[2], f[3], f[5], f[6]);
@@ -84,8 +116,9 @@ def host(tmp_path_factory):
     dp = C.POINTER(C.c_double)
     for name in ("chr_rhs", "chr_rhs_direct", "ham_rhs"):
         getattr(lib, name).argtypes = [C.c_double, C.c_double, dp, dp]
-    for name in ("chr_step", "ham_step"):
+    for name in ("chr_step", "ham_step", "chr_step_vjp"):
         getattr(lib, name).argtypes = [C.c_double, C.c_double, C.c_double, dp, dp]
+    lib.chr_accel_vjp.argtypes = [C.c_double, C.c_double, dp, dp, dp]
     lib.dp45.argtypes = [C.c_double, C.c_double, C.c_double, dp, dp, dp]
     return lib
 
@@ -165,3 +198,47 @@ def test_dp45_attempt_matches_oracle(orc, host, a):
             # e is a difference of two solutions (cancellation): its rounding is
             # absolute, ~ h ulp(f)
             assert np.max(np.abs(e - re)) <= 1e-14 * h * (np.max(np.abs(y[4:])) + 1.0)
+
+
+@pytest.mark.parametrize("a", [0.0, 0.7, 0.998])
+def test_acceleration_vjp_matches_complex_step(orc, host, a):
+    """The reverse mode of the regrouped acceleration (the adjoint's transposed Jacobian)
+    against the oracle: each column of d a / d(r, theta, u) is a central difference of
+    the oracle's right-hand side with a step that balances truncation and rounding
+    (1e-5 of the coordinate: error ~1e-10 of the column's scale), and b^T J is compared
+    column by column."""
+    s0 = sample_states(orc, a, 60, 55)
+    rng = np.random.default_rng(56)
+    for i in range(s0.shape[1]):
+        y = np.ascontiguousarray(s0[:, i])
+        b = np.ascontiguousarray(rng.standard_normal(4))
+        out = np.zeros(6)
+        host.chr_accel_vjp(1.0, a, _p(y), _p(b), _p(out))
+        for j, k in enumerate((1, 2, 4, 5, 6, 7)):
+            e = 1e-5 * max(abs(y[k]), 1e-2)
+            yp, ym = y.copy(), y.copy()
+            yp[k] += e
+            ym[k] -= e
+            col = (orc.rhs(1.0, a, yp)[4:] - orc.rhs(1.0, a, ym)[4:]) / (2 * e)
+            want = b @ col
+            scale = np.abs(b) @ np.abs(col) + 1e-300
+            assert abs(out[j] - want) <= 1e-7 * scale + 1e-12, (i, k, out[j], want)
+
+
+@pytest.mark.parametrize("a", [0.0, 0.9])
+def test_rk4_vjp_is_the_transpose_of_the_oracle_tangent(orc, host, a):
+    """<lam, J v> = <J^T lam, v> for one RK4 step, J v from the oracle's complex-step
+    tangent (exact up to rounding) and J^T lam from the transposed step that the
+    adjoint kernel runs (rk4_vjp with the reverse-mode acceleration)."""
+    s0 = sample_states(orc, a, 64, 57)
+    rng = np.random.default_rng(58)
+    for i in range(s0.shape[1]):
+        y = np.ascontiguousarray(s0[:, i])
+        v = rng.standard_normal(8)
+        lam = rng.standard_normal(8)
+        _, jv = orc.tangent(1.0, a, 0.02, 1, y, v)
+        jt = lam.copy()
+        host.chr_step_vjp(1.0, a, 0.02, _p(y), _p(jt))
+        lhs, rhs_ = lam @ jv, jt @ v
+        scale = np.abs(lam) @ np.abs(jv) + np.abs(jt) @ np.abs(v)
+        assert abs(lhs - rhs_) <= 1e-13 * scale, (i, lhs, rhs_)
