@@ -43,8 +43,8 @@ PEAK_FP32_VECTOR_TFLOPS = 157.3
 # taken again.
 KERNEL_SOURCES = ("integrate.hip", "kerr_device.hpp", "kerr_accel.hpp", "ham_accel.hpp",
                   "persistent.hpp")
-TRAFFIC = {"sources_sha256": "d5cbb2d80a961867e0fd094a668bf39d5de7cd6bdce03ee0df67239f519950a7",
-           "fetch_kib": 36941.5, "fetch_scale": 1048576 / 524307.6875,
+TRAFFIC = {"sources_sha256": "375a77b5c401cbdc379905d6c9c0d2e7bbb08cdb212811a7867217e12a57bbcd",
+           "fetch_kib": 36949.1875, "fetch_scale": 1048576 / 524308.25,
            "write_kib": 73728.0, "write_scale": 1048576 / 1048576.0}
 
 
