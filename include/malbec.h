@@ -55,6 +55,8 @@ extern "C" {
 #define MALBEC_ENOMEM (-2)  /* caller workspace smaller than malbec_workspace_bytes() */
 #define MALBEC_EDEVICE (-3) /* a HIP runtime error (text in malbec_last_error()) */
 #define MALBEC_ENOTSUP (-4) /* valid but unsupported combination */
+#define MALBEC_ESAMPLE (-5) /* malbec_init_particles with strict = 1: some lanes exhausted
+                               max_attempts (their state is NaN, attempts = max_attempts) */
 
 /* ---- lane status (int32 per lane) ------------------------------------------------ */
 #define MALBEC_ACTIVE 0    /* still integrating */
@@ -112,7 +114,9 @@ typedef struct {
 /* Initial-condition recipe (malbec_init_particles). */
 typedef struct {
     int32_t mode;   /* MALBEC_IC_* */
-    int32_t pad0_;
+    int32_t strict; /* CONSTANTS: 1 = count the lanes that exhaust max_attempts on the device,
+                       wait for the stream and return MALBEC_ESAMPLE if there are any (a
+                       blocking call); 0 = report them per lane only (asynchronous) */
     uint64_t seed;  /* SplitMix64 seed: draw k of attempt j of lane i is output
                        (i*2^24 + j*2^4 + k + 1) of the SplitMix64 sequence from `seed` */
     int64_t lane0;  /* global index of lane 0 of this call (sub-batches draw the same numbers) */
@@ -235,7 +239,11 @@ MALBEC_API size_t malbec_workspace_bytes(int32_t op, int64_t n, int32_t aux);
  * Passages: Section 5 IC table (CANONICAL; u^mu = g^{mu nu} p_nu with p_t = -E),
  * Sections 3-4 circular orbits (CIRCULAR), Carter's separated equations (CONSTANTS).
  * Errors: MALBEC_EINVAL on bad arguments; lanes whose sampler is exhausted are
- * reported through attempts == max_attempts and a NaN state, not as an error. */
+ * reported through attempts == max_attempts and a NaN state; with spec->strict = 1
+ * (CONSTANTS mode) the call also counts them on the device, waits for the stream and
+ * returns MALBEC_ESAMPLE when there are any (their number in malbec_last_error()).
+ * The count lives in a file-scope device variable of the library (one per GPU), so
+ * strict calls that overlap on one GPU race; MALBEC_EDEVICE if its lookup fails. */
 MALBEC_API int malbec_init_particles(const malbec_ic_spec *spec, const malbec_batch *b, int64_t n,
                           double *state, double *consts, int64_t *attempts, void *stream);
 

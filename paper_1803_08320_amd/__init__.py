@@ -35,6 +35,7 @@ F64, F32_KAHAN = 0, 1
 FORM_CHRISTOFFEL, FORM_HAMILTONIAN = 0, 1
 IC_CANONICAL, IC_CIRCULAR, IC_CONSTANTS, IC_PARAMS = 0, 1, 2, 3
 OP_INTEGRATE, OP_CAMERA, OP_ADJOINT, OP_ADAPTIVE, OP_ADAPTIVE_ORDER = 1, 2, 3, 4, 5
+OK, EINVAL, ENOMEM, EDEVICE, ENOTSUP, ESAMPLE = 0, -1, -2, -3, -4, -5
 SCHED_INDEX, SCHED_PERIAPSIS, SCHED_BUCKETS = 0, 1, 1024
 NOALLOC_MAX_LANES = 1 << 21
 GRID_F64, GRID_F32 = 0, 1
@@ -77,7 +78,7 @@ class c_batch(C.Structure):
 
 
 class c_ic_spec(C.Structure):
-    _fields_ = [("mode", C.c_int32), ("pad0_", C.c_int32), ("seed", C.c_uint64),
+    _fields_ = [("mode", C.c_int32), ("strict", C.c_int32), ("seed", C.c_uint64),
                 ("lane0", C.c_int64), ("mu2", C.c_double), ("r_lo", C.c_double),
                 ("r_hi", C.c_double), ("dL", C.c_double), ("prograde", C.c_int32),
                 ("e_from_norm", C.c_int32), ("r_range", C.c_double * 2),
@@ -250,9 +251,10 @@ class ICSpec:
     Q_range: Tuple[float, float] = (0.0, 12.0)
     max_attempts: int = 100000
     rows: Optional[torch.Tensor] = field(default=None, repr=False)
+    strict: bool = False  # CONSTANTS: raise (MALBEC_ESAMPLE) if a lane exhausts max_attempts
 
     def to_c(self, n):
-        return c_ic_spec(self.mode, 0, self.seed & 0xFFFFFFFFFFFFFFFF, self.lane0, self.mu2,
+        return c_ic_spec(self.mode, int(self.strict), self.seed & 0xFFFFFFFFFFFFFFFF, self.lane0, self.mu2,
                          self.r_lo, self.r_hi, self.dL, int(self.prograde), int(self.e_from_norm),
                          (C.c_double * 2)(*self.r_range), (C.c_double * 2)(*self.th_range),
                          (C.c_double * 2)(*self.E_range), (C.c_double * 2)(*self.Lz_range),

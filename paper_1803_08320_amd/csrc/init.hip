@@ -9,6 +9,8 @@
 // Random numbers: SplitMix64 (Steele, Lea & Flood 2014) used as a counter-based
 // generator, draw k of attempt j of lane i = output (i*2^24 + j*2^4 + k + 1) of the
 // sequence started at `seed`.
+#include <mutex>
+
 #include "ic_device.hpp"
 #include "internal.hpp"
 
@@ -52,7 +54,14 @@ struct InitArgs {
     double *state;
     double *consts;
     int64_t *attempts;
+    unsigned long long *exhausted;  // strict mode: count of lanes that exhausted the sampler
 };
+
+// Lanes whose rejection sampler ran out of attempts in a strict call (one counter per
+// GPU: each device holds its own copy, found through hipGetSymbolAddress).
+__device__ unsigned long long g_exhausted;
+
+__global__ void zero_exhausted_kernel(unsigned long long *p) { *p = 0ull; }
 
 __global__ void __launch_bounds__(256) init_kernel(InitArgs A, StTable T)
 {
@@ -151,6 +160,7 @@ __global__ void __launch_bounds__(256) init_kernel(InitArgs A, StTable T)
 #pragma unroll
             for (int k = 0; k < 8; ++k) y[k] = __builtin_nan("");
             used = P.max_attempts;
+            if (A.exhausted) atomicAdd(A.exhausted, 1ull);
         }
     }
     if (bad_sid) {
@@ -170,6 +180,29 @@ __global__ void __launch_bounds__(256) init_kernel(InitArgs A, StTable T)
 
 }  // namespace
 
+// The device address of g_exhausted on the current device, looked up once per device
+// (each GPU holds its own copy at its own address; the name itself is a host-side
+// stand-in that must not be passed to a kernel).
+static int exhausted_counter(unsigned long long **out)
+{
+    constexpr int kDevices = 64;
+    static std::mutex mu;
+    static unsigned long long *ptr[kDevices] = {};
+    int dev = 0;
+    MALBEC_HIP_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kDevices)
+        return fail(MALBEC_ENOTSUP, "device %d: the strict sampler count covers %d devices", dev, kDevices);
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[dev]) {
+        void *p = nullptr;
+        MALBEC_HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(g_exhausted)));
+        if (!p) return fail(MALBEC_EDEVICE, "hipGetSymbolAddress returned NULL for the sampler count");
+        ptr[dev] = (unsigned long long *)p;
+    }
+    *out = ptr[dev];
+    return MALBEC_OK;
+}
+
 int launch_init(const malbec_ic_spec &spec, const StTable &T, const int32_t *st_of_lane, int64_t n,
                 double *state, double *consts, int64_t *attempts, hipStream_t s)
 {
@@ -180,9 +213,25 @@ int launch_init(const malbec_ic_spec &spec, const StTable &T, const int32_t *st_
     A.state = state;
     A.consts = consts;
     A.attempts = attempts;
+    A.exhausted = nullptr;
+    const bool strict = spec.strict != 0 && spec.mode == MALBEC_IC_CONSTANTS;
+    if (strict) {
+        int rc = exhausted_counter(&A.exhausted);
+        if (rc) return rc;
+        hipLaunchKernelGGL(zero_exhausted_kernel, dim3(1), dim3(1), 0, s, A.exhausted);
+        MALBEC_LAUNCH_CHECK("zero_exhausted_kernel");
+    }
     const int block = 256;
     hipLaunchKernelGGL(init_kernel, dim3(grid_for(n, block)), dim3(block), 0, s, A, T);
     MALBEC_LAUNCH_CHECK("init_kernel");
+    if (strict) {
+        unsigned long long count = 0;
+        MALBEC_HIP_CHECK(hipMemcpyAsync(&count, A.exhausted, sizeof(count), hipMemcpyDeviceToHost, s));
+        MALBEC_HIP_CHECK(hipStreamSynchronize(s));
+        if (count > 0)
+            return fail(MALBEC_ESAMPLE, "%llu of %lld lanes exhausted max_attempts = %lld", count,
+                        (long long)n, (long long)spec.max_attempts);
+    }
     return MALBEC_OK;
 }
 

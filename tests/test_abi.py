@@ -51,6 +51,7 @@ def test_struct_layout_matches_header(m, tmp_path):
                    "P(malbec_run)P(malbec_camera)P(malbec_adaptive)O(malbec_adaptive, max_attempts)"
                    "P(malbec_grid)O(malbec_grid, r_stop)O(malbec_grid, nodes)O(malbec_grid, node_precision)"
                    "O(malbec_adaptive, steps_per_chunk)O(malbec_adaptive, schedule)O(malbec_ic_spec, rows)O(malbec_ic_spec, max_attempts)"
+                   "O(malbec_ic_spec, strict)printf(\"ESAMPLE %d\\n\", MALBEC_ESAMPLE);"
                    "O(malbec_run, checkpoint_every)O(malbec_run, persistent)O(malbec_run, formulation)"
                    "O(malbec_camera, max_steps)O(malbec_camera, persistent)"
                    "O(malbec_batch, st_of_lane)return 0;}\n")
@@ -73,6 +74,8 @@ def test_struct_layout_matches_header(m, tmp_path):
     assert int(got["malbec_adaptive.schedule"]) == m.c_adaptive.schedule.offset
     assert int(got["malbec_ic_spec.rows"]) == m.c_ic_spec.rows.offset
     assert int(got["malbec_ic_spec.max_attempts"]) == m.c_ic_spec.max_attempts.offset
+    assert int(got["malbec_ic_spec.strict"]) == m.c_ic_spec.strict.offset
+    assert int(got["ESAMPLE"]) == m.ESAMPLE
     assert int(got["malbec_run.checkpoint_every"]) == m.c_run.checkpoint_every.offset
     assert int(got["malbec_run.persistent"]) == m.c_run.persistent.offset
     assert int(got["malbec_run.formulation"]) == m.c_run.formulation.offset

@@ -65,6 +65,39 @@ def test_init_constants_matches_oracle(m, orc):
     assert mixed_rel(state2.cpu().numpy(), s0[:, 5000:5100]).max() < 5e-13
 
 
+def test_init_strict_reports_exhausted_sampler(m, orc):
+    """Lanes whose rejection sampler runs out of attempts: NaN state and attempts =
+    max_attempts per lane (as the oracle's builder, which then returns -5), and with
+    strict = 1 the call itself returns MALBEC_ESAMPLE with their number; a recipe
+    without exhausted lanes passes strict mode."""
+    st = [(1.0, 0.9)]
+    n, max_att = 3001, 40
+    ranges = (KERR_RANGES[0], KERR_RANGES[1], (0.5, 0.98), KERR_RANGES[3], KERR_RANGES[4])
+    rc, s0, _, att0 = orc.ic_constants(6, st, n, ranges, max_attempts=max_att)
+    exh = np.isnan(s0).all(axis=0)  # exhausted (a lane accepted at its last attempt also
+    n_exh = int(exh.sum())          # reports attempts = max_attempts, with a valid state)
+    assert rc == -5 and 0 < n_exh < n and (att0[exh] == max_att).all()
+    spec = m.ICSpec(mode=m.IC_CONSTANTS, seed=6, r_range=ranges[0], th_range=ranges[1],
+                    E_range=ranges[2], Lz_range=ranges[3], Q_range=ranges[4],
+                    max_attempts=max_att)
+    state, _, att = m.init_particles(spec, st, n)
+    att = att.cpu().numpy()
+    assert np.array_equal(att, att0)
+    sh = state.cpu().numpy()
+    assert np.array_equal(np.isnan(sh), np.isnan(s0))
+    spec.strict = True
+    with pytest.raises(m.MalbecError) as e:
+        m.init_particles(spec, st, n)
+    assert e.value.code == m.ESAMPLE and ("%d of %d lanes" % (n_exh, n)) in str(e.value)
+    # the strict call leaves the same per-lane results, and passes where nothing is exhausted
+    spec.strict = False
+    ok_spec = spec_constants(m, 2)
+    ok_spec.strict = True
+    state2, _, att2 = m.init_particles(ok_spec, st, 2000)
+    rc2, _, _, att20 = orc.ic_constants(2, st, 2000, KERR_RANGES)
+    assert rc2 == 0 and np.array_equal(att2.cpu().numpy(), att20)
+
+
 def test_init_circular_and_canonical_match_oracle(m, orc):
     import torch
     st = [(1.0, 0.0)]
