@@ -43,8 +43,8 @@ PEAK_FP32_VECTOR_TFLOPS = 157.3
 # taken again.
 KERNEL_SOURCES = ("integrate.hip", "kerr_device.hpp", "kerr_accel.hpp", "ham_accel.hpp",
                   "persistent.hpp")
-TRAFFIC = {"sources_sha256": "375a77b5c401cbdc379905d6c9c0d2e7bbb08cdb212811a7867217e12a57bbcd",
-           "fetch_kib": 36949.1875, "fetch_scale": 1048576 / 524308.25,
+TRAFFIC = {"sources_sha256": "2bf21cb6e1f799687c9e458269a817d5ae560ad47308ce2db59b3c41a6753d97",
+           "fetch_kib": 36945.25, "fetch_scale": 1048576 / 524308.3125,
            "write_kib": 73728.0, "write_scale": 1048576 / 1048576.0}
 
 

@@ -44,21 +44,21 @@ MAX_SPACETIMES = 64
 # FP64 flops of one RK4 step of one lane (static counts by csrc/flopcount.cpp:
 # add/sub/mul/div 1, fma 2, sincos 2).  Christoffel form: the work of a step is fixed
 # by its direct evaluation (kerr_accel_direct in csrc/kerr_accel.hpp: coefficients, then
-# the contraction), 514; the kernels evaluate the same acceleration regrouped, in 446
+# the contraction), 514; the kernels evaluate the same acceleration regrouped, in 442
 # (FLOPS_PER_STEP_F64_KERNEL).  Hamilton's equations: 336.
 FLOPS_PER_STEP_F64 = 514
-FLOPS_PER_STEP_F64_KERNEL = 446
+FLOPS_PER_STEP_F64_KERNEL = 442
 FLOPS_PER_STEP_F64_HAM = 336
 # FP32-compensated steps (FP32 flops): the stage increment plus d + lo and a two-sum per
 # component (7 each); Christoffel form (direct evaluation, and as the kernel evaluates
 # it) and Hamilton's equations
 FLOPS_PER_STEP_F32K = 562
-FLOPS_PER_STEP_F32K_KERNEL = 494
+FLOPS_PER_STEP_F32K_KERNEL = 490
 FLOPS_PER_STEP_F32K_HAM = 386
 # one Dormand-Prince 5(4) attempt (six right-hand sides and the tableau; csrc/dp45.hpp),
 # direct evaluation of the acceleration, and as the kernel evaluates it
 FLOPS_PER_ATTEMPT_DP45 = 1024
-FLOPS_PER_ATTEMPT_DP45_KERNEL = 922
+FLOPS_PER_ATTEMPT_DP45_KERNEL = 916
 
 
 class MalbecError(RuntimeError):

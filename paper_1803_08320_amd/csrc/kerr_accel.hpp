@@ -177,7 +177,7 @@ MALBEC_HD inline void kerr_accel(T M, T a, T r, T s, T c, T ut, T ur, T uth, T u
     const T sc = s * c;
     const T r2 = r * r;
     const T A = r2 + a2;                    // r^2 + a^2
-    const T rho2 = fma(a2, c * c, r2);      // r^2 + a^2 cos^2
+    const T rho2 = fma(-a2, s2, A);         // r^2 + a^2 cos^2 = A - a^2 sin^2
     const T M2 = M + M;
     const T Delta = fma(-M2, r, A);         // r^2 - 2 M r + a^2
     const T Ds2 = Delta * s2;

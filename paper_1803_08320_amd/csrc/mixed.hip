@@ -126,6 +126,7 @@ struct MixProg {
     struct Lane {
         float hi[8], lo[8];
         Spacetime S;
+        float rs32;  // the largest float not above S.r_stop
         HamConst<double> P64;
         HamConst<float> P32;
         int32_t st, taken;
@@ -143,6 +144,8 @@ struct MixProg {
             }
         }
         L.S = table[sid];
+        L.rs32 = (float)L.S.r_stop;  // r_stop > 0: one step down is the bit pattern minus one
+        if ((double)L.rs32 > L.S.r_stop) L.rs32 = __int_as_float(__float_as_int(L.rs32) - 1);
 #pragma unroll
         for (int k = 0; k < 8; ++k) split(A.state[k * A.n + i], L.hi[k], L.lo[k]);
         if (HAM) {
@@ -180,7 +183,8 @@ struct MixProg {
                 AccelF32 f32{(float)S.M, (float)S.a, {0.0f, 0.0f, 1.0f}};
                 rk4_delta(f32, (float)A.h, L.hi, d, sr);
             }
-            if ((double)sr[0] <= S.r_stop || (double)sr[1] <= S.r_stop || (double)sr[2] <= S.r_stop) {
+            // (double)x <= r_stop exactly when x <= rs32, the largest float not above r_stop
+            if (sr[0] <= L.rs32 || sr[1] <= L.rs32 || sr[2] <= L.rs32) {
                 L.st = kHorizon;
             } else {
                 float nh[8], nl[8];
