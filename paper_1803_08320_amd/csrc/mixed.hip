@@ -191,8 +191,10 @@ struct MixProg {
                 bool ok = true;
 #pragma unroll
                 for (int c = 0; c < 8; ++c) {
+                    // the two-sum's error term of a finite sum is finite (and exact), so
+                    // a finite nh implies a finite nl
                     two_sum(L.hi[c], d[c] + L.lo[c], nh[c], nl[c]);
-                    ok = ok && __builtin_isfinite(nh[c]) && __builtin_isfinite(nl[c]);
+                    ok = ok && __builtin_isfinite(nh[c]);
                 }
                 const double th = (double)nh[2] + (double)nl[2];
                 if (!(ok && th > 0.0 && th < 3.14159265358979323846)) {
