@@ -142,13 +142,19 @@ def test_monitor_is_the_invariant_kernel_every_K_steps(m, orc):
     two = run_mon(m, st, half[0], 0.05, K * chunks // 2, K, monitor=half[3], reset=False,
                   status=half[1], steps=half[2])
     split = run_mon(m, st, s0, 0.05, K * chunks, K, steps_per_chunk=333)
-    for x, y, z in zip(one, two, split):
-        assert np.array_equal(x, y) and np.array_equal(x, z)
+    # the persistent kernel holds a lane's values in LDS between its monitored steps and
+    # takes them from the buffer when resumed
+    half_p = run_mon(m, st, s0, 0.05, K * chunks // 2, K, persistent=True)
+    two_p = run_mon(m, st, half_p[0], 0.05, K * chunks // 2, K, monitor=half_p[3], reset=False,
+                    status=half_p[1], steps=half_p[2], persistent=True)
+    for x, y, z, w in zip(one, two, split, two_p):
+        assert np.array_equal(x, y) and np.array_equal(x, z) and np.array_equal(x, w)
 
 
 def test_f32k_monitor_bounds(m, orc):
     """FP32-compensated state, FP64 monitor: the drift maxima stay within the stated
-    accuracy of that path and include the end state's drift."""
+    accuracy of that path (about 10x the measured p99 of the maxima, 3e-8 in E and
+    1.2e-7 in Q on the 16-spin batch) and include the end state's drift."""
     st = [(1.0, 0.9)]
     rc, s0, c0, _ = orc.ic_constants(84, st, 1000, KERR_RANGES)
     import torch
@@ -157,9 +163,9 @@ def test_f32k_monitor_bounds(m, orc):
     I1 = m.invariants(to_dev(got[0], torch.float64), st).cpu().numpy()
     D = got[3][4:]
     assert np.all(D[:, act] >= np.abs(I1 - got[3][:4])[:, act])
-    assert np.quantile(D[0][act] / np.abs(got[3][0][act]), 0.99) < 1e-5
+    assert np.quantile(D[0][act] / np.abs(got[3][0][act]), 0.99) < 3e-7
     q = act & (c0[2] >= 0.1)
-    assert np.quantile(D[2][q] / np.abs(got[3][2][q]), 0.99) < 1e-4
+    assert np.quantile(D[2][q] / np.abs(got[3][2][q]), 0.99) < 2e-6
 
 
 def test_inactive_lanes_and_empty_calls(m, orc):
