@@ -43,8 +43,8 @@ PEAK_FP32_VECTOR_TFLOPS = 157.3
 # taken again.
 KERNEL_SOURCES = ("integrate.hip", "kerr_device.hpp", "kerr_accel.hpp", "ham_accel.hpp",
                   "persistent.hpp")
-TRAFFIC = {"sources_sha256": "2bf21cb6e1f799687c9e458269a817d5ae560ad47308ce2db59b3c41a6753d97",
-           "fetch_kib": 36945.25, "fetch_scale": 1048576 / 524308.3125,
+TRAFFIC = {"sources_sha256": "485e0c8dedeb376ca0213504e0980e0ac5b9894554f25fb3c51c5e5310e5ab1e",
+           "fetch_kib": 36944.5625, "fetch_scale": 1048576 / 524308.25,
            "write_kib": 73728.0, "write_scale": 1048576 / 1048576.0}
 
 

@@ -194,8 +194,8 @@ struct F64Prog {
         double y1[8], sr[3];
         step_f64<HAM>(L.S, L.P, A.h, L.y, y1, sr);
         ++L.taken;
-        bool accept;
-        L.st = terminate_f64(L.S, A.r_escape, sr, y1, accept);
+        bool accept = true;  // the common outcome of the stop rules first, as rk4_f64_kernel
+        if (!still_active_f64(L.S, A.r_escape, sr, y1)) L.st = terminate_f64(L.S, A.r_escape, sr, y1, accept);
         if (accept) copy8(L.y, y1);
         return L.st != kActive || L.taken == A.n_steps;
     }
