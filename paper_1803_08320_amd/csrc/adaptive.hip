@@ -54,6 +54,10 @@ __device__ __forceinline__ double rpow5(double err)
     return y;
 }
 
+// The acceleration with the trigonometry table read from the block's LDS copy: at the
+// kernels' two waves per SIMD the vector cache's latency would otherwise show.
+using AccelAd = AccelF64T<StageTrigT<false, TabLds>>;
+
 struct AdProg {
     const AdArgs &A;
     const Spacetime *table;  // LDS copy of the spacetimes (mixed batch)
@@ -72,7 +76,7 @@ struct AdProg {
     __device__ __forceinline__ void deriv0(Lane &L)
     {
         const Spacetime S = space(L);
-        AccelF64 f{S.M, S.a, {}};
+        AccelAd f{S.M, S.a, {}};
         f(0, L.y[1], L.y[2], L.y[4], L.y[5], L.y[6], L.y[7], L.k1a[0], L.k1a[1], L.k1a[2],
           L.k1a[3]);
     }
@@ -120,7 +124,7 @@ struct AdProg {
         }
         // stage 0 of the rotation base is the start point: sin and cos evaluated fresh
         const Spacetime S = space(L);
-        AccelF64 f{S.M, S.a, {}};
+        AccelAd f{S.M, S.a, {}};
         {
             double s, c;
             f.trig(0, L.y[2], s, c);
@@ -189,6 +193,7 @@ __global__ void __launch_bounds__(256) dp45_kernel(AdArgs A, StTable T)
 {
     __shared__ Spacetime lds_st[kMaxSt];
     for (int k = threadIdx.x; k < T.n_st; k += blockDim.x) lds_st[k] = T.st[k];
+    TabLds::fill();
     __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= A.n) return;
@@ -207,6 +212,7 @@ __global__ void __launch_bounds__(256) dp45_persistent_kernel(AdArgs A, StTable 
 {
     __shared__ Spacetime lds_st[kMaxSt];
     for (int k = threadIdx.x; k < T.n_st; k += blockDim.x) lds_st[k] = T.st[k];
+    TabLds::fill();
     __syncthreads();
     AdProg P{A, lds_st, MULTI, T.n_st, T.st[0]};
     persistent_loop(P, A.n, counter, chunk);

@@ -43,7 +43,7 @@ struct AdjArgs {
 // register count, measured 4 % slower at the one wave per SIMD that 65,536 lanes give.)
 struct AdjAccel {
     double M, a;
-    StageTrigT<true> trig;
+    StageTrigT<true, TabLds> trig;
     double Ys[4][6], sk[4], ck[4];
     __device__ __forceinline__ double &Y(int st, int k) { return Ys[st][k]; }
     __device__ __forceinline__ void keep() {}
@@ -70,10 +70,13 @@ template <bool MULTI>
 __global__ void __launch_bounds__(256) adjoint_kernel(AdjArgs A, StTable T)
 {
     __shared__ Spacetime lds_st[kMaxSt];
-    if (MULTI) {
+    if (MULTI)
         for (int k = threadIdx.x; k < T.n_st; k += blockDim.x) lds_st[k] = T.st[k];
-        __syncthreads();
-    }
+    // one wave per SIMD (the kernel's register count): nothing would cover the latency
+    // of the trigonometry table's reads through the vector cache, which the workspace
+    // streams through, so each block reads its own LDS copy
+    TabLds::fill();
+    __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= A.n) return;
     int32_t sid = MULTI ? A.st_of_lane[i] : 0;
@@ -103,7 +106,7 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjArgs A, StTable T)
             for (int k = 0; k < 8; ++k) A.scratch[((int64_t)j * 8 + k) * n + i] = y[k];
             if (j + 1 < len) {
                 double y1[8], sr[3];
-                rk4_step_f64(S, A.h, y, y1, sr);
+                rk4_step_f64<true, TabLds>(S, A.h, y, y1, sr);
 #pragma unroll
                 for (int k = 0; k < 8; ++k) y[k] = y1[k];
             }
@@ -123,7 +126,7 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjArgs A, StTable T)
             if (g0 + j == taken - 1 && status != kActive) {
                 // terminal step: its result was kept only if the termination rule accepted it
                 double y1[8], sr[3];
-                rk4_step_f64(S, A.h, y, y1, sr);
+                rk4_step_f64<true, TabLds>(S, A.h, y, y1, sr);
                 terminate_f64(S, A.r_escape, sr, y1, accepted);
             }
             if (accepted) {

@@ -60,7 +60,9 @@ __device__ __forceinline__ void pixel_ray(const CamArgs &A, int64_t p, double y[
     y[4] = -u[0]; y[5] = -u[1]; y[6] = -u[2]; y[7] = -u[3];
 }
 
-// One step of a camera ray.  Rules in order: a stage point at r <= r_stop ->
+// One step of a camera ray (the trigonometry table read from the block's LDS copy,
+// which both camera kernels fill first: measured about 1.5 % faster than reading it
+// through the vector cache).  Rules in order: a stage point at r <= r_stop ->
 // HORIZON (y kept); unusable result -> NONFINITE (y kept); crossing of the
 // equatorial plane with r_c in [disk_r_in, disk_r_out] -> DISK; r <= r_stop ->
 // HORIZON; r >= r_escape -> ESCAPE.  Crossing: the sign of cos(theta) differs
@@ -72,7 +74,7 @@ __device__ __forceinline__ int32_t camera_step(const CamArgs &A, double y[8], in
     const double q = fma(fma(-A.h_r0, q0, y[1]), A.inv_h_r0, q0);
     const double h = A.h0 * fmax(1.0, q);
     double y1[8], sr[3];
-    rk4_step_f64<false>(A.S, h, y, y1, sr);
+    rk4_step_f64<false, TabLds>(A.S, h, y, y1, sr);
     ++n;
     if (sr[0] <= A.S.r_stop || sr[1] <= A.S.r_stop || sr[2] <= A.S.r_stop) return kHorizon;
     if (!usable(y1)) return kNonfinite;
@@ -112,6 +114,8 @@ __device__ __forceinline__ void write_result(const CamArgs &A, int64_t p, int32_
 // One thread per pixel, each traced to the end.
 __global__ void __launch_bounds__(256) camera_plain_kernel(CamArgs A)
 {
+    TabLds::fill();
+    __syncthreads();
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= A.npix) return;
     double y[8];
@@ -143,6 +147,8 @@ __global__ void __launch_bounds__(256) camera_persistent_kernel(CamArgs A,
                                                                 unsigned long long *counter,
                                                                 const double *y0)
 {
+    TabLds::fill();
+    __syncthreads();
     const unsigned lane = threadIdx.x & 63u;
     int64_t p = -1;  // pixel in flight, -1 = idle
     double y[8];

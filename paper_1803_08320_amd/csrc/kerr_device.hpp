@@ -7,6 +7,7 @@
 
 #include "ham_accel.hpp"
 #include "kerr_accel.hpp"
+#include "sincos_table.hpp"
 
 namespace malbec {
 
@@ -35,11 +36,13 @@ struct Spacetime {
 // so the addition does not cancel; cos is accurate in absolute terms, which is how the
 // right-hand sides use it).  At the step sizes of the workloads (h <= 0.1 with
 // |u^theta| well below 1) stage points stay within 0.04 of the step's start.
-// SHORT: sin d through d^5 and cos d through d^6 for |d| <= kRotMaxShort, where the
-// truncation is below 2e-18 absolute (d^7 / 7!) and 3e-21 (d^8 / 8!): with
-// sin(theta) >= 2 |d| that is below 1.1e-16 relative in sin(theta + d).
+// SHORT: sin d through d^5 and cos d through d^4 for |d| <= kRotMaxShort, where the
+// truncation is below 1.6e-20 absolute (d^7 / 7!) and 2.2e-17 (d^6 / 6!): with
+// sin(theta) >= 2 |d| that is below 0.2 ulp relative in sin(theta + d).  Measured on
+// gfx950 from the table base below, with half of 4M offsets at the limit: sin within
+// 4.9 ulp (99.9 % within 2.0), cos within 1.3 ulp of 1.
 constexpr double kRotMax = 0.04;
-constexpr double kRotMaxShort = 0.01;
+constexpr double kRotMaxShort = 0.005;
 
 // a * b + c as one three-address v_fma_f64 with the constant addend c read from a
 // scalar register pair.  Used for the polynomial steps below: the compiler's own
@@ -63,18 +66,18 @@ template <bool SHORT = false>
 __device__ __forceinline__ void rotate(double s0, double c0, double d, double &s, double &c)
 {
     const double d2 = d * d;
-    // sin d = d + d^3 ps(d^2),  cos d = 1 - d^2 pc(d^2)
+    // sin d = d + d^3 ps(d^2);  cos d = 1 + d^2 pc(d^2) (SHORT), 1 - d^2 pc(d^2)
     double ps, pc;
     if (SHORT) {
         ps = fma3c(d2, kF5, -kF3);
-        pc = fma3c(d2, -kF6, kF4);
+        pc = fma(d2, kF4, -kF2);  // -1/2 is an inline constant: kF4 takes the scalar operand
     } else {
         ps = fma3c(d2, -kF7, kF5);
         ps = fma3c(d2, ps, -kF3);
         pc = fma3c(d2, -kF8, kF6);
         pc = fma3c(d2, pc, -kF4);
+        pc = fma(d2, pc, kF2);
     }
-    pc = fma(d2, pc, SHORT ? -kF2 : kF2);
     const double sd = fma(d * d2, ps, d);
     const double cd = SHORT ? fma(d2, pc, 1.0) : fma(-d2, pc, 1.0);
     s = fma(s0, cd, c0 * sd);
@@ -111,18 +114,50 @@ __device__ __forceinline__ double sincos_reduce(double th, double &sx, double &c
     return k;
 }
 
-// sin and cos of theta in (0, pi) (every accepted state has theta there): k is 0, 1
-// or 2, and the quadrant swap is k = 0: (sx, cx); 1: (cx, -sx); 2: (-sx, -cx).
-__device__ __forceinline__ void sincos_0pi(double th, double &s, double &c)
+// sin and cos of theta in [0, pi] (every accepted state has theta in (0, pi)) from the
+// nearest angle of the table, theta_j = j pi / N: j = rint(theta N / pi), formed as
+// the low word of theta N / pi + 1.5 * 2^52 (one rounding, to nearest), d = theta -
+// theta_j with the split step (|d| <= pi / 2N < kRotMaxShort), and the short rotation
+// of the correctly rounded (sin theta_j, cos theta_j) by d.  The rotation cancels by
+// at most one bit (for j >= 1, sin theta >= sin theta_j / 2; j = 0 gives sin d
+// itself): measured on gfx950 over 4M angles in [0, pi], sin within 2.3 ulp (99.9 %
+// within 1.3) and cos within 0.8 ulp of 1, against 1.3 and 0.5 for the minimax
+// evaluation of sincos_reduce, at 18 instructions instead of 29.  An angle outside
+// [0, pi] (not a state the integrators produce) reads an entry within the table and
+// gives meaningless values.
+// Where the table is read from: the global copy, through the vector cache (TabGlobal),
+// or a kernel's own copy in LDS (for kernels at one wave per SIMD, where no other wave
+// covers the cache's latency).  Both hold the same values, so results are the same.
+struct TabGlobal {
+    __device__ static __forceinline__ const double *row(uint32_t j) { return kTrigTab[j]; }
+};
+// The LDS copy: one array per kernel that uses it (a function-scope LDS variable), which
+// every thread of the block fills (fill(), then a barrier) before any thread reads it.
+struct TabLds {
+    __device__ static __forceinline__ double (*table())[2]
+    {
+        __shared__ double t[kTrigTabN + 1][2];
+        return t;
+    }
+    __device__ static __forceinline__ const double *row(uint32_t j) { return table()[j]; }
+    __device__ static __forceinline__ void fill()
+    {
+        for (int k = threadIdx.x; k < 2 * (kTrigTabN + 1); k += blockDim.x)
+            (&table()[0][0])[k] = (&kTrigTab[0][0])[k];
+    }
+};
+
+template <typename Tab = TabGlobal>
+__device__ __forceinline__ void sincos_tab(double th, double &s, double &c)
 {
-    double sx, cx;
-    const double k = sincos_reduce(th, sx, cx);
-    // (s, c) = A (sx, cx) + B (cx, -sx) with (A, B) = (1 - k, k (2 - k)): (1, 0), (0, 1)
-    // and (-1, 0) for k = 0, 1, 2 (products by 0 and +-1 and sums with 0 are exact)
-    const double A = 1.0 - k;
-    const double B = k * (2.0 - k);
-    s = fma(A, sx, B * cx);
-    c = fma(A, cx, -B * sx);
+    constexpr double kRound = 6755399441055744.0;  // 1.5 * 2^52
+    const double jb = fma(th, kTrigTabInvStep, kRound);
+    const double j = jb - kRound;
+    const double d = fma(-j, kTrigStepLo, fma(-j, kTrigStepHi, th));
+    uint32_t ji = (uint32_t)__double_as_longlong(jb);
+    ji = ji < (uint32_t)kTrigTabN ? ji : (uint32_t)kTrigTabN;
+    const double *e = Tab::row(ji);
+    rotate<true>(e[0], e[1], d, s, c);
 }
 
 // sin and cos of any moderate theta (|theta| < 1e6; stage points may leave (0, pi)):
@@ -136,15 +171,15 @@ __device__ __forceinline__ void sincos_any(double th, double &s, double &c)
     c = ((q + 1) & 2) ? -cc : cc;
 }
 
-// Reference angle of the stage rotations: theta_b with its sin and cos (a fresh
-// evaluation) and the largest |d| = |theta - theta_b| that the rotation by d may take
+// Reference angle of the stage rotations: theta_b with its sin and cos (from the
+// table) and the largest |d| = |theta - theta_b| that the rotation by d may take
 // from it, min(kRotMax, sin(theta_b) / 2) (kRotMaxShort with the SHORT polynomials).
-template <bool SHORT>
+template <bool SHORT, typename Tab = TabGlobal>
 struct TrigBase {
     double th, s, c, lim;
     __device__ __forceinline__ void set(double theta)
     {
-        sincos_0pi(theta, s, c);
+        sincos_tab<Tab>(theta, s, c);
         th = theta;
         lim = fmin(SHORT ? kRotMaxShort : kRotMax, 0.5 * s);
     }
@@ -164,12 +199,12 @@ struct TrigBase {
 // step's own theta and keeps them as the base; the later stages of the same step rotate
 // that pair, so the trigonometry of a step depends on the step's start state alone (and
 // rotations never chain from step to step).  SHORT: the short rotation polynomials,
-// for fixed steps whose stage points stay within h |u^theta| <= 0.01 of the start (the
-// Kerr bound-orbit workloads at h = 0.02: below 0.004); larger offsets fall back to a
-// fresh evaluation.
-template <bool SHORT>
+// for fixed steps whose stage points stay within h |u^theta| <= 0.005 of the start
+// (the Kerr bound-orbit workloads at h = 0.02: below 0.004); larger offsets fall back
+// to a fresh evaluation.
+template <bool SHORT, typename Tab = TabGlobal>
 struct StageTrigT {
-    TrigBase<SHORT> B;
+    TrigBase<SHORT, Tab> B;
     __device__ __forceinline__ void operator()(int stage, double th, double &s, double &c)
     {
         if (stage == 0) {
@@ -201,12 +236,12 @@ using AccelF64 = AccelF64T<StageTrig>;
 
 // One FP64 RK4 step (Christoffel form).  SHORT = true for the fixed-step integrators
 // (small stage offsets), false for steps whose stage points move further (the camera's
-// h = h0 max(1, r / h_r0)).
-template <bool SHORT = true>
+// h = h0 max(1, r / h_r0)).  Tab: where the trigonometry table is read from.
+template <bool SHORT = true, typename Tab = TabGlobal>
 __device__ __forceinline__ void rk4_step_f64(const Spacetime &S, double h, const double y[8],
                                              double y1[8], double sr[3])
 {
-    AccelF64T<StageTrigT<SHORT>> f{S.M, S.a, {}};
+    AccelF64T<StageTrigT<SHORT, Tab>> f{S.M, S.a, {}};
     rk4_step(f, h, y, y1, sr);
 }
 
