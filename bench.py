@@ -44,7 +44,7 @@ PEAK_FP32_VECTOR_TFLOPS = 157.3
 KERNEL_SOURCES = ("integrate.hip", "kerr_device.hpp", "kerr_accel.hpp", "ham_accel.hpp",
                   "persistent.hpp", "sincos_table.hpp")
 TRAFFIC = {"sources_sha256": "fee7ccaa2b55343fe19ab522488261a72ad5b321389af1bc33cb5c11d537440a",
-           "fetch_kib": 36959.75, "fetch_scale": 1048576 / 524307.9375,
+           "fetch_kib": 36960.0625, "fetch_scale": 1048576 / 524307.5625,
            "write_kib": 73728.0, "write_scale": 1048576 / 1048576.0}
 
 

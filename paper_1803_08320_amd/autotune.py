@@ -147,9 +147,12 @@ def lookup_camera(cam: Camera):
     return tuple(e["shape"]) if e else None
 
 
-def camera_shape(cam: Camera, sample=256, refresh=False):
+def camera_shape(cam: Camera, sample=1024, refresh=False):
     """Best (block, steps_per_chunk) for the persistent camera kernel (cached), timed on a
-    sample x sample image of the same camera."""
+    sample x sample image of the same camera (the best of two launches after a warm-up).
+    The default 1024 x 1024 sample fills the device several times over, as the full image
+    does; on a 256 x 256 one (a single wave per SIMD, 2 ms launches) the choice between
+    the shapes, a few per cent apart, followed the timing noise."""
     key = _camera_key(cam)
     with _lock:
         e = _load().get(key)
@@ -161,7 +164,7 @@ def camera_shape(cam: Camera, sample=256, refresh=False):
     for blk in BLOCKS:
         for ch in CHUNKS:
             c = Camera(**{**small.__dict__, "block": blk, "steps_per_chunk": ch})
-            times[(blk, ch)] = _time(lambda: trace_camera(c), reps=1)
+            times[(blk, ch)] = _time(lambda: trace_camera(c), reps=2)
     best = min(times, key=times.get)
     with _lock:
         cache = dict(_load())
