@@ -36,21 +36,31 @@ __device__ __forceinline__ void sincos_f32(float th, float &s, float &c)
     c = ((q + 1) & 2) ? -cc : cc;
 }
 
-// FP32 sin and cos of the stage theta.  Stage 0 evaluates them (sincos_f32); later
-// stages rotate that pair by the small angle difference (Taylor terms through d^5 /
-// d^6, truncation below 1e-10 for |d| <= 0.125, far under FP32 rounding).
+// FP32 sin and cos of the stage theta.  Stage 0 evaluates them (sincos_f32) and sets
+// the rotation limit min(0.01, sin(theta_0) / 2); later stages rotate that pair by the
+// small angle difference d, with sin d = d - d^3/6 and cos d = 1 - d^2/2 (truncation
+// below 8.4e-13 and 4.2e-10 absolute for |d| <= 0.01, far under FP32 rounding; the
+// second bound keeps sin(theta_0 + d) >= sin(theta_0) / 2), or evaluate afresh beyond
+// the limit.
 struct StageTrigF32 {
-    float th0, s0, c0;
+    float th0, s0, c0, lim;
     __device__ __forceinline__ void operator()(int stage, float th, float &s, float &c)
     {
-        const float d = th - th0;
-        if (stage == 0 || !(fabsf(d) <= 0.125f && fabsf(d) <= 0.5f * s0)) {
+        if (stage == 0) {
             sincos_f32(th, s, c);
-            if (stage == 0) { th0 = th; s0 = s; c0 = c; }
+            th0 = th;
+            s0 = s;
+            c0 = c;
+            lim = fminf(0.01f, 0.5f * s);
+            return;
+        }
+        const float d = th - th0;
+        if (!(fabsf(d) <= lim)) {
+            sincos_f32(th, s, c);
         } else {
             const float d2 = d * d;
-            const float sd = fmaf(d * d2, fmaf(d2, 1.0f / 120.0f, -1.0f / 6.0f), d);
-            const float cd = fmaf(d2, fmaf(d2, fmaf(d2, -1.0f / 720.0f, 1.0f / 24.0f), -0.5f), 1.0f);
+            const float sd = fmaf(d * d2, -1.0f / 6.0f, d);
+            const float cd = fmaf(d2, -0.5f, 1.0f);
             s = fmaf(s0, cd, c0 * sd);
             c = fmaf(c0, cd, -s0 * sd);
         }
@@ -170,17 +180,19 @@ struct MixProg {
                 rk4_step_f64(S, A.h, y, y1, sr);
             bool accept;
             L.st = terminate_f64(S, A.r_escape, sr, y1, accept);
-            if (accept) {
+            // a step that is not accepted ends the lane (HORIZON at a stage point, or
+            // NONFINITE), which keeps y: splitting y again gives a pair whose sum is y
+            // exactly, so the stored state is the same, while hi and lo need not stay
+            // live across the FP64 step (16 registers fewer)
 #pragma unroll
-                for (int c = 0; c < 8; ++c) split(y1[c], L.hi[c], L.lo[c]);
-            }
+            for (int c = 0; c < 8; ++c) split(accept ? y1[c] : y[c], L.hi[c], L.lo[c]);
         } else {
             float d[8], sr[3];
             if (HAM) {
-                HamF32 f32{(float)S.M, (float)S.a, L.P32, {0.0f, 0.0f, 1.0f}};
+                HamF32 f32{(float)S.M, (float)S.a, L.P32, {0.0f, 0.0f, 1.0f, 0.0f}};
                 rk4_ham_delta(f32, (float)A.h, L.hi, d, sr);
             } else {
-                AccelF32 f32{(float)S.M, (float)S.a, {0.0f, 0.0f, 1.0f}};
+                AccelF32 f32{(float)S.M, (float)S.a, {0.0f, 0.0f, 1.0f, 0.0f}};
                 rk4_delta(f32, (float)A.h, L.hi, d, sr);
             }
             // (double)x <= r_stop exactly when x <= rs32, the largest float not above r_stop
@@ -225,8 +237,12 @@ struct MixProg {
     }
 };
 
+// The Christoffel-form kernels are held to 128 registers, four waves per SIMD (the
+// FP64 zone step sets the peak; the FP32 step alone needs about 80); the Hamiltonian
+// form's zone step needs about 150 and keeps the compiler's default (three waves).
 template <bool MULTI, bool HAM>
-__global__ void __launch_bounds__(256) rk4_f32k_kernel(MixArgs A, StTable T)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HAM ? 1 : 4, HAM ? 8 : 4)))
+rk4_f32k_kernel(MixArgs A, StTable T)
 {
     __shared__ Spacetime lds_st[kMaxSt];
     for (int k = threadIdx.x; k < T.n_st; k += blockDim.x) lds_st[k] = T.st[k];
@@ -242,9 +258,8 @@ __global__ void __launch_bounds__(256) rk4_f32k_kernel(MixArgs A, StTable T)
 }
 
 template <bool MULTI, bool HAM>
-__global__ void __launch_bounds__(256) rk4_f32k_persistent_kernel(MixArgs A, StTable T,
-                                                                  unsigned long long *counter,
-                                                                  int32_t chunk)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HAM ? 1 : 4, HAM ? 8 : 4)))
+rk4_f32k_persistent_kernel(MixArgs A, StTable T, unsigned long long *counter, int32_t chunk)
 {
     __shared__ Spacetime lds_st[kMaxSt];
     for (int k = threadIdx.x; k < T.n_st; k += blockDim.x) lds_st[k] = T.st[k];
