@@ -214,7 +214,7 @@ def _build_and_run(tmp_path, compiler, src_name, src, extra):
 @pytest.mark.skipif(not _have("gcc"), reason="gcc not found")
 def test_oracle_under_address_and_undefined_sanitizers(tmp_path):
     """Every oracle entry point the tests use, on small inputs, one thread (the OpenMP
-    pragmas are ignored in this build)."""
+    pragmas are ignored without -fopenmp)."""
     _build_and_run(tmp_path, "gcc", "oracle_driver.c", ORACLE_DRIVER,
                    [os.path.join(ROOT, "oracle", "malbec_oracle.c"), "-std=gnu11",
                     "-ffp-contract=off", "-Wno-unknown-pragmas"])
