@@ -229,6 +229,30 @@ def test_edge_cases(m, orc):
     assert np.array_equal(zero[0], s0[:, 4:])
 
 
+def test_start_angles_across_the_trigonometry_table(m, orc):
+    """Start angles theta0 at the kernels' sin/cos table's nodes j pi / 320, between
+    them, next to both poles (where the stage rotations fall back to a fresh
+    evaluation) and at the equator, with the other components of sampled orbits:
+    200 steps against the oracle.  Lanes that leave (0, pi) or blow up near a pole end
+    NONFINITE on both sides (ties and guarded lanes are counted by compare)."""
+    st = [(1.0, 0.9)]
+    step = math.pi / 320
+    angles = [1e-6, 1e-4, 3e-3, 0.5 * step, step, 1.5 * step, 2 * step, 0.25, 0.5,
+              math.pi / 2 - 1e-12, math.pi / 2, math.pi / 2 + 1e-12, 1.0, 2.0,
+              math.pi - 2 * step, math.pi - 1.5 * step, math.pi - step, math.pi - 0.5 * step,
+              math.pi - 3e-3, math.pi - 1e-4, math.pi - 1e-6]
+    rng = np.random.default_rng(41)
+    angles += list(rng.uniform(0.0, math.pi, 64 - len(angles)))
+    rc, s0, _, _ = orc.ic_constants(9, st, len(angles), KERR_RANGES)
+    s0 = s0.copy()
+    s0[2] = angles
+    s0[6] *= 0.1  # a slower u^theta, so that the near-pole lanes take some steps
+    got = run_gpu(m, st, s0, 0.02, 200)
+    ref = orc.integrate(st, s0, 0.02, 200)
+    compare(orc, st, s0, *got, *ref, oracle_rerun(orc, st, 0.02, 200),
+            label="start angles across the sin/cos table")
+
+
 def test_plunging_lanes_termination_parity(m, orc):
     """Schwarzschild draws with the Kerr ranges: a large fraction plunges; the horizon
     step of every lane must match the oracle."""
