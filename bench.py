@@ -43,7 +43,7 @@ PEAK_FP32_VECTOR_TFLOPS = 157.3
 # taken again.
 KERNEL_SOURCES = ("integrate.hip", "kerr_device.hpp", "kerr_accel.hpp", "ham_accel.hpp",
                   "persistent.hpp", "sincos_table.hpp")
-TRAFFIC = {"sources_sha256": "fee7ccaa2b55343fe19ab522488261a72ad5b321389af1bc33cb5c11d537440a",
+TRAFFIC = {"sources_sha256": "5a6ab0341c68de51e9c473087ee15a8d581b8cf3b3e74fcb06994aca22ca6b95",
            "fetch_kib": 36960.0625, "fetch_scale": 1048576 / 524307.5625,
            "write_kib": 73728.0, "write_scale": 1048576 / 1048576.0}
 

@@ -114,20 +114,9 @@ __device__ __forceinline__ double sincos_reduce(double th, double &sx, double &c
     return k;
 }
 
-// sin and cos of theta in [0, pi] (every accepted state has theta in (0, pi)) from the
-// nearest angle of the table, theta_j = j pi / N: j = rint(theta N / pi), formed as
-// the low word of theta N / pi + 1.5 * 2^52 (one rounding, to nearest), d = theta -
-// theta_j with the split step (|d| <= pi / 2N < kRotMaxShort), and the short rotation
-// of the correctly rounded (sin theta_j, cos theta_j) by d.  The rotation cancels by
-// at most one bit (for j >= 1, sin theta >= sin theta_j / 2; j = 0 gives sin d
-// itself): measured on gfx950 over 4M angles in [0, pi], sin within 2.3 ulp (99.9 %
-// within 1.3) and cos within 0.8 ulp of 1, against 1.3 and 0.5 for the minimax
-// evaluation of sincos_reduce, at 18 instructions instead of 29.  An angle outside
-// [0, pi] (not a state the integrators produce) reads an entry within the table and
-// gives meaningless values.
 // Where the table is read from: the global copy, through the vector cache (TabGlobal),
-// or a kernel's own copy in LDS (for kernels at one wave per SIMD, where no other wave
-// covers the cache's latency).  Both hold the same values, so results are the same.
+// or a kernel's own copy in LDS (for kernels at one or two waves per SIMD, where too few
+// other waves cover the cache's latency).  Both hold the same values, so results are the same.
 struct TabGlobal {
     __device__ static __forceinline__ const double *row(uint32_t j) { return kTrigTab[j]; }
 };
@@ -147,6 +136,17 @@ struct TabLds {
     }
 };
 
+// sin and cos of theta in [0, pi] (every accepted state has theta in (0, pi)) from the
+// nearest angle of the table, theta_j = j pi / N: j = rint(theta N / pi), formed as
+// the low word of theta N / pi + 1.5 * 2^52 (one rounding, to nearest), d = theta -
+// theta_j with the split step (|d| <= pi / 2N < kRotMaxShort), and the short rotation
+// of the correctly rounded (sin theta_j, cos theta_j) by d.  The rotation cancels by
+// at most one bit (for j >= 1, sin theta >= sin theta_j / 2; j = 0 gives sin d
+// itself): measured on gfx950 over 4M angles in [0, pi], sin within 2.3 ulp (99.9 %
+// within 1.3) and cos within 0.8 ulp of 1, against 1.3 and 0.5 for the minimax
+// evaluation of sincos_reduce, at 18 instructions instead of 29.  An angle outside
+// [0, pi] (not a state the integrators produce) reads an entry within the table and
+// gives meaningless values.
 template <typename Tab = TabGlobal>
 __device__ __forceinline__ void sincos_tab(double th, double &s, double &c)
 {
